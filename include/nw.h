@@ -1,0 +1,142 @@
+/*
+ * libnw -- global (Needleman-Wunsch) alignment with a linear gap on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method (paper Section 2): the score grid has one extra row and column
+ * ((m+1) x (n+1) cells, Sec. 2.1); H(0,0) = 0 and the first row and column
+ * fall by one gap per cell (Sec. 2.2); every other cell takes
+ *     H(i,j) = max( H(i-1,j-1) + s(a_i,b_j), H(i-1,j) + gap, H(i,j-1) + gap )
+ * (Sec. 2.3, Eq. 1, read as the standard linear-gap recurrence), with
+ * s = match when a_i == b_j and mismatch otherwise.  Backtracking starts in
+ * the bottom-right cell and follows the argmax (Sec. 2.4); moves use the
+ * paper's direction codes (Sec. 3.1): 1 diagonal, 2 vertical (a_i against a
+ * gap), 3 horizontal (a gap against b_j).  Among tied moves the library
+ * always takes diagonal, then vertical, then horizontal, so every call
+ * returns one fixed optimal path.
+ *
+ * Conventions shared by every entry point:
+ *  - Sequence a (length m) labels rows, sequence b (length n) labels columns.
+ *  - Symbols are nucleotide codes 0..3 stored one per byte.  Only equality
+ *    matters; the kernels read the two low bits of each byte, so values
+ *    above 3 alias and are a caller error.
+ *  - Unless stated otherwise every pointer is a DEVICE pointer (memory from
+ *    hipMalloc or a torch CUDA tensor on the current device), and every call
+ *    is asynchronous on `stream` (a hipStream_t; NULL = the null stream).
+ *    Outputs are valid once the stream has been synchronised.
+ *  - The caller owns every buffer, including the workspace `ws`, which must
+ *    stay allocated and untouched until the call's work on `stream` is done.
+ *    Query its size with the matching *_workspace_size function.  The
+ *    library allocates no device memory in these calls.
+ *  - Paths are written in forward order, from (0,0) to (m,n).  A path has
+ *    between max(m,n) and m+n moves.
+ *  - Scores are int32.  Arguments are checked on the host before any GPU
+ *    work is queued; a non-zero status means nothing was queued.
+ *  - Overflow guard: (max(|match|,|mismatch|) + |gap|) * (m + n) must stay
+ *    below 2^27, and the diagonal step constant 4*(s - 2*gap) + 2 must fit
+ *    in a signed byte for s = match and s = mismatch, else NW_ERANGE.
+ *  - Calls on distinct streams with distinct workspaces may run concurrently.
+ */
+#ifndef NW_H
+#define NW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Scoring constants (paper Sec. 2.3): match +1, mismatch -1, gap -1. */
+typedef struct nw_scoring {
+    int32_t match;
+    int32_t mismatch;
+    int32_t gap;
+} nw_scoring;
+
+/* Move codes (paper Sec. 3.1). */
+enum { NW_MOVE_D = 1, NW_MOVE_U = 2, NW_MOVE_L = 3 };
+
+/* Status codes. */
+enum {
+    NW_OK = 0,
+    NW_EINVAL = -1,  /* null pointer, negative length or count, bad flag   */
+    NW_ERANGE = -2,  /* lengths or constants exceed the overflow guard      */
+    NW_ENOSPC = -3,  /* path capacity or workspace too small                */
+    NW_EDEVICE = -4, /* HIP error while queueing work                       */
+    NW_ENOTSUP = -5  /* no supported GPU (not gfx950) on the current device */
+};
+
+/* Flags. */
+#define NW_SCORE_ONLY 0x1u /* no traceback: paths, path_off, path_len may be NULL */
+
+/* Human-readable text for a status code (static storage). */
+const char *nw_strerror(int status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int nw_version(void);
+
+/* ------------------------------------------------------------------------
+ * One pair (paper Sec. 2; the single-alignment kernel of Sec. 3.1).
+ *
+ * nw_align_workspace_size: bytes of workspace nw_align needs for lengths
+ * (m, n) and `flags`; written to *bytes (a host pointer).
+ *
+ * nw_align: a[m], b[n] (device, codes 0..3); *score (device int32) gets
+ * H(m,n); unless NW_SCORE_ONLY, path[path_cap] (device) gets the moves and
+ * *path_len (device int64) their number.  path_cap >= m + n is required
+ * (NW_ENOSPC otherwise).  m == 0 or n == 0 is valid.
+ * ------------------------------------------------------------------------ */
+int nw_align_workspace_size(int64_t m, int64_t n, uint32_t flags, size_t *bytes);
+
+int nw_align(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n, nw_scoring sc,
+             uint32_t flags, int32_t *score, uint8_t *path, int64_t path_cap,
+             int64_t *path_len, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Many independent pairs in one persistent launch (the data-parallel form of
+ * the paper's multiple-alignment workload, Sec. 3.2).
+ *
+ * Pair k is a = pool[a_off[k] .. a_off[k]+a_len[k]) against
+ * b = pool[b_off[k] .. b_off[k]+b_len[k]).  pool, a_off, a_len, b_off,
+ * b_len are device arrays.  max_len (host) bounds every a_len[k] and
+ * b_len[k]; the workspace is sized for it.  A pair that exceeds max_len is
+ * skipped: scores[k] = INT32_MIN and path_len[k] = -1.
+ *
+ * Outputs (device): scores[npairs]; unless NW_SCORE_ONLY, pair k's moves go
+ * to paths[path_off[k] ..] (path_off: device int64, caller-computed, with
+ * room for a_len[k] + b_len[k] moves) and their count to path_len[k].
+ * ------------------------------------------------------------------------ */
+int nw_align_batch_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags, size_t *bytes);
+
+int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
+                   const int32_t *a_len, const int64_t *b_off, const int32_t *b_len,
+                   int32_t max_len, nw_scoring sc, uint32_t flags, int32_t *scores,
+                   uint8_t *paths, const int64_t *path_off, int32_t *path_len, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * All-pairs score matrix for the centre-star multiple alignment front end
+ * (paper Sec. 3.2, Eq. 2): out[i*nseq + j] (device int32, nseq x nseq,
+ * row-major) = score of sequence i (rows) against sequence j (columns) for
+ * all i != j, computed once per unordered pair (n(n-1)/2 alignments) and
+ * mirrored; out[i*nseq + i] is the score of sequence i against itself,
+ * computed by the same recurrence (len[i] * match whenever match >= mismatch
+ * and match >= 2*gap).  Sequence k = pool[off[k] .. off[k]+len[k]); max_len
+ * (host) bounds every len[k]; an entry whose sequence exceeds it is
+ * INT32_MIN.  nseq*(nseq+1)/2 must fit in int32 (NW_ERANGE otherwise).
+ * ------------------------------------------------------------------------ */
+int nw_allpairs_workspace_size(int32_t nseq, int32_t max_len, size_t *bytes);
+
+int nw_allpairs_scores(int32_t nseq, const uint8_t *pool, const int64_t *off,
+                       const int32_t *len, int32_t max_len, nw_scoring sc, int32_t *out,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Release host-side caches (tuning tables).  Safe to call at any time when
+ * no library call is in flight. */
+void nw_release_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NW_H */

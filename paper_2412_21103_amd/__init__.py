@@ -1,0 +1,188 @@
+"""Python binding for libnw (Needleman-Wunsch with a linear gap on MI355X).
+
+Argument marshalling only: every step of the alignment runs in the HIP
+kernels of ``libnw.so``.  Tensors must be CUDA (HIP) tensors on the current
+device; work is queued on torch's current stream unless ``stream`` is given.
+The library must have been built (``__graft_entry__.build()``); importing
+this package without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+__all__ = [
+    "Scoring", "NWError", "PAPER_SCORING", "lib", "align", "align_batch", "allpairs",
+    "align_workspace_size", "batch_workspace_size", "allpairs_workspace_size",
+    "declared_functions", "MOVE_D", "MOVE_U", "MOVE_L", "SCORE_ONLY",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libnw.so")
+_HEADER = os.path.join(os.path.dirname(_HERE), "include", "nw.h")
+
+MOVE_D, MOVE_U, MOVE_L = 1, 2, 3
+SCORE_ONLY = 0x1
+PAPER_SCORING = (1, -1, -1)
+
+NW_OK, NW_EINVAL, NW_ERANGE, NW_ENOSPC, NW_EDEVICE, NW_ENOTSUP = 0, -1, -2, -3, -4, -5
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap", ctypes.c_int32)]
+
+
+class NWError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {lib().nw_strerror(status).decode()} (status {status})")
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_sz = ctypes.c_size_t
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(_LIB_PATH)
+        L.nw_strerror.argtypes = [ctypes.c_int]
+        L.nw_strerror.restype = ctypes.c_char_p
+        L.nw_version.restype = ctypes.c_int
+        L.nw_align_workspace_size.argtypes = [_i64, _i64, _u32, ctypes.POINTER(_sz)]
+        L.nw_align.argtypes = [_vp, _i64, _vp, _i64, Scoring, _u32, _vp, _vp, _i64, _vp, _vp, _sz, _vp]
+        L.nw_align_batch_workspace_size.argtypes = [_i32, _i32, _u32, ctypes.POINTER(_sz)]
+        L.nw_align_batch.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _u32, _vp, _vp,
+                                     _vp, _vp, _vp, _sz, _vp]
+        L.nw_allpairs_workspace_size.argtypes = [_i32, _i32, ctypes.POINTER(_sz)]
+        L.nw_allpairs_scores.argtypes = [_i32, _vp, _vp, _vp, _i32, Scoring, _vp, _vp, _sz, _vp]
+        L.nw_release_caches.restype = None
+        _lib = L
+    return _lib
+
+
+def declared_functions():
+    """Names of the functions include/nw.h declares."""
+    text = open(_HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nw_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(st: int, where: str):
+    if st != NW_OK:
+        raise NWError(st, where)
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else _vp(0)
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _sc(scoring):
+    if isinstance(scoring, Scoring):
+        return scoring
+    return Scoring(*[int(x) for x in scoring])
+
+
+def _dev():
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def align_workspace_size(m: int, n: int, flags: int = 0) -> int:
+    out = _sz(0)
+    _check(lib().nw_align_workspace_size(int(m), int(n), int(flags), ctypes.byref(out)), "nw_align_workspace_size")
+    return int(out.value)
+
+
+def batch_workspace_size(npairs: int, max_len: int, flags: int = 0) -> int:
+    out = _sz(0)
+    _check(lib().nw_align_batch_workspace_size(int(npairs), int(max_len), int(flags), ctypes.byref(out)),
+           "nw_align_batch_workspace_size")
+    return int(out.value)
+
+
+def allpairs_workspace_size(nseq: int, max_len: int) -> int:
+    out = _sz(0)
+    _check(lib().nw_allpairs_workspace_size(int(nseq), int(max_len), ctypes.byref(out)),
+           "nw_allpairs_workspace_size")
+    return int(out.value)
+
+
+def _workspace(nbytes, workspace):
+    if workspace is not None and workspace.numel() >= nbytes:
+        return workspace
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=_dev())
+
+
+def align(a: torch.Tensor, b: torch.Tensor, scoring=PAPER_SCORING, score_only: bool = False,
+          workspace: torch.Tensor | None = None, stream=None):
+    """Align one pair.  Returns ``(score, path, path_len)`` device tensors:
+    int32[1], uint8[m+n] (moves from (0,0); only the first path_len are set)
+    and int64[1].  ``path`` and ``path_len`` are None with ``score_only``."""
+    m, n = int(a.numel()), int(b.numel())
+    flags = SCORE_ONLY if score_only else 0
+    dev = _dev()
+    ws = _workspace(align_workspace_size(m, n, flags), workspace)
+    score = torch.empty(1, dtype=torch.int32, device=dev)
+    path = None if score_only else torch.empty(max(m + n, 1), dtype=torch.uint8, device=dev)
+    plen = None if score_only else torch.empty(1, dtype=torch.int64, device=dev)
+    st = lib().nw_align(_ptr(a), m, _ptr(b), n, _sc(scoring), flags, _ptr(score), _ptr(path),
+                        (m + n) if path is not None else 0, _ptr(plen), _ptr(ws), ws.numel(),
+                        _stream(stream))
+    _check(st, "nw_align")
+    return score, path, plen
+
+
+def align_batch(pool: torch.Tensor, a_off: torch.Tensor, a_len: torch.Tensor, b_off: torch.Tensor,
+                b_len: torch.Tensor, max_len: int, scoring=PAPER_SCORING, score_only: bool = False,
+                path_off: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                stream=None):
+    """Align many pairs from one pool.  Returns ``(scores, paths, path_off, path_len)``;
+    the last three are None with ``score_only``.  When ``path_off`` is None it is
+    the prefix sum of a_len + b_len."""
+    npairs = int(a_len.numel())
+    flags = SCORE_ONLY if score_only else 0
+    dev = _dev()
+    ws = _workspace(batch_workspace_size(npairs, max_len, flags), workspace)
+    scores = torch.empty(npairs, dtype=torch.int32, device=dev)
+    paths = plen = None
+    if not score_only:
+        caps = a_len.to(torch.int64) + b_len.to(torch.int64)
+        if path_off is None:
+            path_off = torch.zeros(npairs, dtype=torch.int64, device=dev)
+            if npairs > 1:
+                path_off[1:] = torch.cumsum(caps, 0)[:-1]
+        total = int((path_off[-1] + caps[-1]).item()) if npairs else 1
+        paths = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+        plen = torch.empty(npairs, dtype=torch.int32, device=dev)
+    st = lib().nw_align_batch(npairs, _ptr(pool), _ptr(a_off), _ptr(a_len), _ptr(b_off), _ptr(b_len),
+                              int(max_len), _sc(scoring), flags, _ptr(scores), _ptr(paths),
+                              _ptr(path_off), _ptr(plen), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "nw_align_batch")
+    return scores, paths, path_off, plen
+
+
+def allpairs(pool: torch.Tensor, off: torch.Tensor, lens: torch.Tensor, max_len: int,
+             scoring=PAPER_SCORING, workspace: torch.Tensor | None = None, stream=None):
+    """nseq x nseq int32 score matrix (device)."""
+    nseq = int(lens.numel())
+    dev = _dev()
+    ws = _workspace(allpairs_workspace_size(nseq, max_len), workspace)
+    out = torch.empty((nseq, nseq), dtype=torch.int32, device=dev)
+    st = lib().nw_allpairs_scores(nseq, _ptr(pool), _ptr(off), _ptr(lens), int(max_len), _sc(scoring),
+                                  _ptr(out), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "nw_allpairs_scores")
+    return out

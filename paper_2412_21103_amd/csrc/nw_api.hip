@@ -1,0 +1,233 @@
+// C-ABI entry points of libnw: argument checks on the host, workspace sizing
+// and dispatch to the kernels.  No GPU work is queued unless every check
+// passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "nw_internal.h"
+
+namespace nw {
+
+Consts dirs_consts(const nw_scoring& sc) {
+    return Consts{4 * (sc.match - 2 * sc.gap) + 2, 4 * (sc.mismatch - 2 * sc.gap) + 2, sc.gap};
+}
+Consts score_consts(const nw_scoring& sc) {
+    return Consts{sc.match - 2 * sc.gap, sc.mismatch - 2 * sc.gap, sc.gap};
+}
+
+int device_info(DeviceInfo* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return NW_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return NW_EDEVICE;
+    out->device = dev;
+    out->cus = prop.multiProcessorCount;
+    out->supported = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    return out->supported ? NW_OK : NW_ENOTSUP;
+}
+
+// Host checks shared by all entry points.
+static bool fits_byte(int32_t v) { return v >= -127 && v <= 127; }
+
+static int check_scoring(const nw_scoring& sc, bool dirs) {
+    const int64_t big = 1 << 20;
+    if (std::llabs(sc.match) > big || std::llabs(sc.mismatch) > big || std::llabs(sc.gap) > big)
+        return NW_ERANGE;
+    const Consts K = dirs ? dirs_consts(sc) : score_consts(sc);
+    if (!fits_byte(K.kdm) || !fits_byte(K.kdx)) return NW_ERANGE;
+    return NW_OK;
+}
+
+static int check_lengths(int64_t m, int64_t n, const nw_scoring& sc) {
+    if (m < 0 || n < 0) return NW_EINVAL;
+    if (m > INT32_MAX / 4 || n > INT32_MAX / 4) return NW_ERANGE;
+    const int64_t c = std::max(std::llabs(sc.match), std::llabs(sc.mismatch)) + std::llabs(sc.gap);
+    if (c * (m + n) >= (int64_t(1) << 27)) return NW_ERANGE;
+    return NW_OK;
+}
+
+}  // namespace nw
+
+using namespace nw;
+
+extern "C" {
+
+const char* nw_strerror(int status) {
+    switch (status) {
+        case NW_OK: return "success";
+        case NW_EINVAL: return "invalid argument (null pointer, negative length or count, bad flag)";
+        case NW_ERANGE: return "lengths or scoring constants exceed the overflow guard";
+        case NW_ENOSPC: return "path capacity or workspace too small";
+        case NW_EDEVICE: return "HIP error while queueing work";
+        case NW_ENOTSUP: return "current device is not a gfx950 GPU";
+        default: return "unknown status";
+    }
+}
+
+int nw_version(void) { return 100; }
+
+void nw_release_caches(void) {}
+
+// ---------------------------------------------------------------- one pair
+
+static const size_t kDescBytes = 1024;  // one-pair descriptor at the front of ws
+
+int nw_align_workspace_size(int64_t m, int64_t n, uint32_t flags, size_t* bytes) {
+    if (!bytes || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    if (m < 0 || n < 0) return NW_EINVAL;
+    if (m > INT32_MAX / 4 || n > INT32_MAX / 4) return NW_ERANGE;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    const int32_t ml = (int32_t)std::max<int64_t>(std::max(m, n), 1);
+    *bytes = kDescBytes + batch_workspace_bytes(1, ml, !(flags & NW_SCORE_ONLY), di);
+    return NW_OK;
+}
+
+__global__ void k_single_desc(int64_t* d64, int32_t* d32, int64_t b_off, int32_t m, int32_t n) {
+    if (threadIdx.x == 0) {
+        d64[0] = 0;       // a_off
+        d64[1] = b_off;   // b_off
+        d64[2] = 0;       // path_off
+        d32[0] = m;       // a_len
+        d32[1] = n;       // b_len
+    }
+}
+
+int nw_align(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, nw_scoring sc,
+             uint32_t flags, int32_t* score, uint8_t* path, int64_t path_cap,
+             int64_t* path_len, void* ws, size_t ws_bytes, void* stream) {
+    if (flags & ~NW_SCORE_ONLY) return NW_EINVAL;
+    const bool dirs = !(flags & NW_SCORE_ONLY);
+    int st = check_lengths(m, n, sc);
+    if (st) return st;
+    if ((m > 0 && !a) || (n > 0 && !b) || !score || !ws) return NW_EINVAL;
+    if (dirs && (!path_len || (m + n > 0 && !path))) return NW_EINVAL;
+    if (dirs && path_cap < m + n) return NW_ENOSPC;
+    if ((st = check_scoring(sc, dirs))) return st;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    const int32_t ml = (int32_t)std::max<int64_t>(std::max(m, n), 1);
+    const size_t need = kDescBytes + batch_workspace_bytes(1, ml, dirs, di);
+    if (ws_bytes < need) return NW_ENOSPC;
+
+    uint8_t* base = (uint8_t*)ws;
+    int64_t* d64 = (int64_t*)base;
+    int32_t* d32 = (int32_t*)(base + 64);
+    const uint8_t* pa = (m > 0) ? a : b;
+    const uint8_t* pb = (n > 0) ? b : pa;
+    if (!pa) {  // both empty: any valid device pointer works as a pool base
+        pa = pb = (const uint8_t*)ws;
+    }
+    const int64_t b_off = (int64_t)((intptr_t)pb - (intptr_t)pa);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_single_desc, dim3(1), dim3(64), 0, s, d64, d32, b_off, (int32_t)m, (int32_t)n);
+
+    BatchJob J{};
+    J.allpairs = false;
+    J.njobs = 1;
+    J.pool = pa;
+    J.a_off = d64;
+    J.b_off = d64 + 1;
+    J.a_len = d32;
+    J.b_len = d32 + 1;
+    J.max_len = ml;
+    J.sc = sc;
+    J.dirs = dirs;
+    J.scores = score;
+    J.paths = path;
+    J.path_off = d64 + 2;
+    J.path_len = nullptr;
+    J.path_len64 = dirs ? path_len : nullptr;
+    return launch_batch(J, base + kDescBytes, ws_bytes - kDescBytes, s, di);
+}
+
+// ------------------------------------------------------------------ batch
+
+int nw_align_batch_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags, size_t* bytes) {
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    *bytes = batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di);
+    return NW_OK;
+}
+
+int nw_align_batch(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
+                   const int32_t* a_len, const int64_t* b_off, const int32_t* b_len,
+                   int32_t max_len, nw_scoring sc, uint32_t flags, int32_t* scores,
+                   uint8_t* paths, const int64_t* path_off, int32_t* path_len, void* ws,
+                   size_t ws_bytes, void* stream) {
+    if (npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    const bool dirs = !(flags & NW_SCORE_ONLY);
+    int st = check_lengths(max_len, max_len, sc);
+    if (st) return st;
+    if ((st = check_scoring(sc, dirs))) return st;
+    if (npairs == 0) return NW_OK;
+    if (!pool || !a_off || !a_len || !b_off || !b_len || !scores || !ws) return NW_EINVAL;
+    if (dirs && (!paths || !path_off || !path_len)) return NW_EINVAL;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    BatchJob J{};
+    J.allpairs = false;
+    J.njobs = npairs;
+    J.pool = pool;
+    J.a_off = a_off;
+    J.a_len = a_len;
+    J.b_off = b_off;
+    J.b_len = b_len;
+    J.max_len = std::max(max_len, 1);
+    J.sc = sc;
+    J.dirs = dirs;
+    J.scores = scores;
+    J.paths = paths;
+    J.path_off = path_off;
+    J.path_len = dirs ? path_len : nullptr;
+    return launch_batch(J, ws, ws_bytes, (hipStream_t)stream, di);
+}
+
+// -------------------------------------------------------------- all pairs
+
+int nw_allpairs_workspace_size(int32_t nseq, int32_t max_len, size_t* bytes) {
+    if (!bytes || nseq < 0 || max_len < 0) return NW_EINVAL;
+    if ((int64_t)nseq * (nseq + 1) / 2 > INT32_MAX) return NW_ERANGE;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    *bytes = batch_workspace_bytes((int32_t)((int64_t)nseq * (nseq + 1) / 2), std::max(max_len, 1),
+                                   false, di);
+    return NW_OK;
+}
+
+int nw_allpairs_scores(int32_t nseq, const uint8_t* pool, const int64_t* off, const int32_t* len,
+                       int32_t max_len, nw_scoring sc, int32_t* out, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (nseq < 0 || max_len < 0) return NW_EINVAL;
+    if ((int64_t)nseq * (nseq + 1) / 2 > INT32_MAX) return NW_ERANGE;
+    int st = check_lengths(max_len, max_len, sc);
+    if (st) return st;
+    if ((st = check_scoring(sc, false))) return st;
+    if (nseq == 0) return NW_OK;
+    if (!pool || !off || !len || !out || !ws) return NW_EINVAL;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    BatchJob J{};
+    J.allpairs = true;
+    J.njobs = (int32_t)((int64_t)nseq * (nseq + 1) / 2);
+    J.nseq = nseq;
+    J.pool = pool;
+    J.a_off = off;
+    J.a_len = len;
+    J.b_off = off;
+    J.b_len = len;
+    J.max_len = std::max(max_len, 1);
+    J.sc = sc;
+    J.dirs = false;
+    J.matrix = out;
+    return launch_batch(J, ws, ws_bytes, (hipStream_t)stream, di);
+}
+
+}  // extern "C"

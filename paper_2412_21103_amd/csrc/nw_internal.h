@@ -1,0 +1,57 @@
+// Host-side internals shared by the libnw translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/nw.h"
+
+namespace nw {
+
+// Substitution-table bytes for the two value domains (see nw_common.h).
+struct Consts {
+    int32_t kdm, kdx;  // per-cell diagonal term for match / mismatch
+    int32_t gap;
+};
+
+Consts dirs_consts(const nw_scoring& sc);   // V domain: 4(s - 2 gap) + 2
+Consts score_consts(const nw_scoring& sc);  // W domain: s - 2 gap
+
+// Device facts needed to size persistent grids.
+struct DeviceInfo {
+    int device;
+    int cus;
+    bool supported;
+};
+int device_info(DeviceInfo* out);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Persistent batch engine (nw_batch.hip).
+struct BatchJob {
+    // pairs: explicit arrays; all-pairs: nseq sequences, jobs are i <= j
+    bool allpairs;
+    int32_t njobs;
+    int32_t nseq;
+    const uint8_t* pool;
+    const int64_t* a_off;
+    const int32_t* a_len;
+    const int64_t* b_off;
+    const int32_t* b_len;
+    int32_t max_len;
+    nw_scoring sc;
+    bool dirs;
+    int32_t* scores;     // pairs mode
+    uint8_t* paths;
+    const int64_t* path_off;
+    int32_t* path_len;
+    int64_t* path_len64; // single-pair calls report an int64 length
+    int32_t* matrix;     // all-pairs mode
+};
+
+size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di);
+int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t stream,
+                 const DeviceInfo& di);
+
+}  // namespace nw

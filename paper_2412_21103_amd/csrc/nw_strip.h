@@ -1,0 +1,235 @@
+// Column-strip wavefront engine and windowed traceback (one wave each).
+//
+// A strip is 64*C consecutive columns of one pair.  Lane l owns columns
+// j0 + C*l + k (k = 0..C-1) and at step t works on row i = t - l + 1, so the
+// wave sweeps the strip top to bottom along a skewed anti-diagonal front: the
+// cell's vertical and diagonal inputs are the lane's own registers from the
+// previous step, the horizontal input of column k > 0 is the value just
+// produced for column k-1, and the horizontal input of column 0 is the
+// previous step's last-column value of lane l-1, moved across lanes with one
+// DPP wave shift.  Lane 0 takes that value from a 64-entry queue register R:
+// R is shifted left one lane per step, so lane 0 consumes the next row's
+// left-boundary value while lane 63 appends its own last-column value, which
+// is the strip's right boundary for the next strip.  Every 16 steps lanes
+// 48..63 of R are written out and refilled.
+//
+// The substitution term comes from a per-row table in LDS: for row i the word
+// holds four signed bytes, byte y = term(a_i == y).  Lane (l, k) reads byte
+// b_j of the row it is on with one ds_read_i8.  Rows outside 1..m hold -128,
+// which freezes the lanes that are above or below the matrix (see
+// nw_common.h), so the sweep needs no per-lane predicates.
+//
+// Directions: each lane shifts the 2-bit tag of every cell of column k into a
+// 32-bit accumulator; after 16 steps lane l stores its C words contiguously,
+// giving the layout  dirs[strip][group g][lane l][column k]  (one word per
+// 16 consecutive steps of one column).  Step t of lane l is row t - l + 1, so
+// cell (i, j) lives in word (g = (i-1+l) / 16) at bits 2*((i-1+l) % 16).
+#pragma once
+
+#include "nw_common.h"
+
+namespace nw {
+
+constexpr int kWinRows = 192;   // rows per table window
+constexpr int kWinGroups = 8;   // 16-step groups served by one window
+
+template <int C>
+struct StripShape {
+    static constexpr int kCols = kWave * C;
+    // LDS words per wave: two table windows, or the traceback window
+    static constexpr int kLdsWords = (2 * kWinRows > 64 * C) ? 2 * kWinRows : 64 * C;
+};
+
+// Lane 63 finishes row m at step m + 62, and its value enters the queue at the
+// start of step m + 63, which must lie in a group that the loop runs (the
+// group's end flushes it).  So the sweep runs floor((m + 63) / 16) + 1 groups.
+__host__ __device__ __forceinline__ int groups_for_rows(int m) { return (m + 79) >> 4; }
+__host__ __device__ __forceinline__ int steps_for_rows(int m) { return groups_for_rows(m) << 4; }
+
+// Fill one table window: word p <-> row wlo + p.
+__device__ __forceinline__ void write_window(uint32_t* win, const uint8_t* a, int m, int wlo,
+                                             int kdm, int kdx, int lane) {
+#pragma unroll
+    for (int e = 0; e < kWinRows / kWave; ++e) {
+        int p = lane + kWave * e;
+        int r = wlo + p;
+        uint32_t w = kSentinelWord;
+        if (r >= 1 && r <= m) w = row_word(a[r - 1], kdm, kdx);
+        win[p] = w;
+    }
+}
+
+// Boundary input for row r: from bin (previous strip's right column) or the
+// first column of the grid; rows beyond m get 0, which never wins.
+__device__ __forceinline__ int32_t boundary_in(const int32_t* bin, int r, int m, int32_t vinit) {
+    if (r > m) return 0;
+    return bin ? bin[r] : vinit;
+}
+
+// Sweep one strip.  Returns, per lane, V (or W) of its column `ksel` after
+// the last row (the frozen final value).
+template <int C, bool DIRS>
+__device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, int m, const uint8_t* __restrict__ b,
+                               int n, int j0, int kdm, int kdx, int32_t vinit,
+                               const int32_t* bin, int32_t* bout, uint32_t* __restrict__ dirs,
+                               uint32_t* lds, int ksel) {
+    const int lane = lane_id();
+    int32_t V[C];
+    uint32_t acc[C];
+    uint32_t bcode[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        V[k] = vinit;
+        acc[k] = 0;
+        int j = j0 + C * lane + k;
+        bcode[k] = (j < n) ? (uint32_t)(b[j] & 3) : 0u;
+    }
+    int32_t Dg = vinit;
+    int32_t R = boundary_in(bin, lane + 1, m, vinit);
+
+    const int NG = groups_for_rows(m);
+    // window 0 covers groups [0, 8): rows [-63, 129)
+    int g0 = 0;
+    int cur = 0;
+    write_window(lds, a, m, -63, kdm, kdx, lane);
+    // prefetch the next window's symbols
+    uint8_t pf[kWinRows / kWave];
+#pragma unroll
+    for (int e = 0; e < kWinRows / kWave; ++e) {
+        int r = 16 * kWinGroups - 63 + lane + kWave * e;
+        pf[e] = (r >= 1 && r <= m) ? a[r - 1] : (uint8_t)0xFF;
+    }
+
+    const int8_t* lds8 = reinterpret_cast<const int8_t*>(lds);
+    for (int g = 0; g < NG; ++g) {
+        int gg = g - g0;
+        if (gg == kWinGroups) {
+            // switch windows: materialise the prefetched rows, then prefetch the next
+            cur ^= 1;
+            g0 += kWinGroups;
+            gg = 0;
+            uint32_t* win = lds + cur * kWinRows;
+#pragma unroll
+            for (int e = 0; e < kWinRows / kWave; ++e) {
+                int p = lane + kWave * e;
+                win[p] = (pf[e] == 0xFF) ? kSentinelWord : row_word(pf[e], kdm, kdx);
+            }
+#pragma unroll
+            for (int e = 0; e < kWinRows / kWave; ++e) {
+                int r = 16 * (g0 + kWinGroups) - 63 + lane + kWave * e;
+                pf[e] = (r >= 1 && r <= m) ? a[r - 1] : (uint8_t)0xFF;
+            }
+        }
+        // byte address of (row of step 16g, this lane, column k) in the window;
+        // the mask shows the compiler the address is non-negative so the
+        // per-step offsets 4u fold into the ds_read immediate
+        const uint32_t base = (uint32_t)(cur * kWinRows * 4 + 4 * (64 - lane) + 64 * gg);
+        uint32_t addr[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) addr[k] = (base + bcode[k]) & 0x7FFFu;
+
+        // boundary values for the refill at the end of this group
+        const int rin = 16 * (g + 1) + 1 + lane;
+        const int32_t Rin = (bin && lane >= 48 && rin <= m) ? bin[rin] : (rin <= m ? vinit : 0);
+
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int32_t Lr = dpp_from_left(R, V[C - 1]);
+            R = dpp_from_right(V[C - 1], R);
+            int32_t left = Lr;
+            int32_t diag = Dg;
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                int32_t kd = (int32_t)lds8[addr[k] + 4 * u];
+                int32_t up = V[k];
+                int32_t cD = diag + kd;
+                int32_t v;
+                if constexpr (DIRS) {
+                    int32_t r = imax3(cD, up + 1, left);
+                    acc[k] = shift_in_tag((uint32_t)r, acc[k]);
+                    v = clear_tag(r);
+                } else {
+                    v = imax3(cD, up, left);
+                }
+                diag = up;
+                V[k] = v;
+                left = v;
+            }
+            Dg = Lr;
+        }
+        if constexpr (DIRS) {
+            uint32_t* dst = dirs + ((size_t)g * kWave + lane) * C;
+#pragma unroll
+            for (int k = 0; k < C; ++k) dst[k] = acc[k];
+        }
+        {
+            const int r = 16 * g + lane - 111;
+            if (bout && lane >= 48 && r >= 1 && r <= m) bout[r] = R;
+            R = (lane >= 48) ? Rin : R;
+        }
+    }
+    int32_t out = V[0];
+#pragma unroll
+    for (int k = 1; k < C; ++k)
+        if (k == ksel) out = V[k];
+    return out;
+}
+
+// Walk the stored directions of one pair from (m, n) back to (0, 0), one wave,
+// through a small LDS window of 4 groups x 16 lanes x C words anchored at the
+// current cell.  rev[q] gets the q-th move counted from the end.  Returns the
+// number of moves, or -1 if a stored tag is invalid.
+template <int C>
+__device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, int m, int n, int groups_per_strip,
+                             uint32_t* lds, uint8_t* __restrict__ rev) {
+    const int lane = lane_id();
+    int i = m, j = n;
+    int64_t q = 0;
+    int sw = -1, gw = 0, lw = 0;
+    constexpr int kCols = kWave * C;
+    while (i > 0 && j > 0) {
+        const int col0 = j - 1;
+        const int s = col0 / kCols;
+        const int w = col0 - s * kCols;
+        const int l = w / C;
+        const int k = w - l * C;
+        const int t = i - 1 + l;
+        const int g = t >> 4;
+        if (s != sw || g > gw || g < gw - 3 || l > lw || l < lw - 15) {
+            sw = s;
+            gw = g;
+            lw = l;
+            const int gq = gw - 3 + (lane >> 4);
+            const int lq = lw - 15 + (lane & 15);
+            if (gq >= 0 && lq >= 0) {
+                const uint32_t* src = dirs + (((size_t)sw * groups_per_strip + gq) * kWave + lq) * C;
+#pragma unroll
+                for (int kk = 0; kk < C; ++kk) lds[lane * C + kk] = src[kk];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        const int slot = ((g - gw + 3) << 4) + (l - lw + 15);
+        const uint32_t word = (uint32_t)uniform((int32_t)lds[slot * C + k]);
+        const int tag = (int)((word >> (2 * (t & 15))) & 3u);
+        if (tag == 0) return -1;
+        const int mv = 4 - tag;
+        rev[q] = (uint8_t)mv;  // every lane stores the same byte
+        ++q;
+        if (mv == 1) {
+            --i;
+            --j;
+        } else if (mv == 2) {
+            --i;
+        } else {
+            --j;
+        }
+    }
+    // first column: vertical moves; first row: horizontal moves
+    for (int x = lane; x < i; x += kWave) rev[q + x] = 2;
+    q += i;
+    for (int x = lane; x < j; x += kWave) rev[q + x] = 3;
+    q += j;
+    return q;
+}
+
+}  // namespace nw

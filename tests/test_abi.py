@@ -1,0 +1,68 @@
+"""The C-ABI library loads, exports every function include/nw.h declares, and
+rejects bad arguments on the host (no GPU needed for any of this)."""
+import ctypes
+import subprocess
+
+import pytest
+
+nwp = pytest.importorskip("paper_2412_21103_amd")
+
+
+def test_exports_every_declared_function():
+    declared = nwp.declared_functions()
+    assert {"nw_align", "nw_align_batch", "nw_allpairs_scores", "nw_strerror"} <= set(declared)
+    out = subprocess.run(["nm", "-D", "--defined-only", nwp._LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [f for f in declared if f not in exported]
+    assert not missing, missing
+    L = nwp.lib()
+    for f in declared:
+        assert hasattr(L, f)
+
+
+def test_strerror_and_version():
+    L = nwp.lib()
+    for st in [0, -1, -2, -3, -4, -5, 7]:
+        assert isinstance(L.nw_strerror(st), bytes)
+    assert L.nw_version() >= 100
+
+
+def _align(**kw):
+    args = dict(a=1, m=4, b=1, n=4, sc=nwp.Scoring(1, -1, -1), flags=0, score=1, path=1, cap=8,
+                plen=1, ws=1, wsb=1 << 30, stream=None)
+    args.update(kw)
+    vp = ctypes.c_void_p
+    return nwp.lib().nw_align(vp(args["a"]), args["m"], vp(args["b"]), args["n"], args["sc"],
+                              args["flags"], vp(args["score"]), vp(args["path"]), args["cap"],
+                              vp(args["plen"]), vp(args["ws"]), args["wsb"], vp(args["stream"]))
+
+
+def test_host_argument_checks():
+    # every one of these is rejected before any HIP call
+    assert _align(m=-1) == nwp.NW_EINVAL
+    assert _align(a=0) == nwp.NW_EINVAL
+    assert _align(b=0) == nwp.NW_EINVAL
+    assert _align(score=0) == nwp.NW_EINVAL
+    assert _align(plen=0) == nwp.NW_EINVAL
+    assert _align(ws=0) == nwp.NW_EINVAL
+    assert _align(cap=7) == nwp.NW_ENOSPC
+    assert _align(flags=0x80) == nwp.NW_EINVAL
+    # diagonal constant 4*(s - 2 gap) + 2 outside a signed byte
+    assert _align(sc=nwp.Scoring(40, -1, -1)) == nwp.NW_ERANGE
+    # overflow guard on lengths
+    assert _align(m=1 << 27, n=1 << 27, cap=1 << 28) == nwp.NW_ERANGE
+    vp = ctypes.c_void_p
+    L = nwp.lib()
+    assert L.nw_align_batch(-1, vp(1), vp(1), vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), 0,
+                            vp(1), vp(1), vp(1), vp(1), vp(1), 1, vp(0)) == nwp.NW_EINVAL
+    assert L.nw_align_batch(4, vp(0), vp(1), vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), 0,
+                            vp(1), vp(1), vp(1), vp(1), vp(1), 1, vp(0)) == nwp.NW_EINVAL
+    assert L.nw_align_batch(4, vp(1), vp(1), vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), 0,
+                            vp(1), vp(0), vp(1), vp(1), vp(1), 1, vp(0)) == nwp.NW_EINVAL
+    assert L.nw_align_batch(0, vp(0), vp(0), vp(0), vp(0), vp(0), 10, nwp.Scoring(1, -1, -1), 0,
+                            vp(0), vp(0), vp(0), vp(0), vp(0), 0, vp(0)) == nwp.NW_OK
+    assert L.nw_allpairs_scores(-3, vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), vp(1), vp(1), 1,
+                                vp(0)) == nwp.NW_EINVAL
+    assert L.nw_allpairs_scores(70000, vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), vp(1), vp(1),
+                                1, vp(0)) == nwp.NW_ERANGE

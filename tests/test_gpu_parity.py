@@ -1,0 +1,103 @@
+"""Bit-exact parity of the HIP path against the CPU oracle (scores and paths)."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import (config_allpairs, config_batch, config_single, mutate, pack_pairs,
+                       pack_seqs, random_seq)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from gpu_util import gpu_align, gpu_allpairs, gpu_batch, say  # noqa: E402
+
+P = (1, -1, -1)
+EDGE = [0, 1, 2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024,
+        1025]
+
+
+def check_pair(a, b, sc=P, tag=""):
+    s_ref, p_ref = oracle.align(a, b, sc)
+    s, p = gpu_align(a, b, sc)
+    assert s == s_ref, (tag, len(a), len(b), s, s_ref)
+    assert p.tolist() == p_ref.tolist(), (tag, len(a), len(b))
+    s2, _ = gpu_align(a, b, sc, score_only=True)
+    assert s2 == s_ref, (tag, "score-only", len(a), len(b))
+
+
+def test_single_pair_config_1024():
+    p = config_single()
+    say("single 1024x1024")
+    check_pair(p.a[0], p.b[0], P, "config_single")
+
+
+def test_single_pair_edge_shapes():
+    rng = np.random.default_rng(21)
+    for m in EDGE:
+        for n in [0, 1, 17, 64, 65, 300, 513, 1025]:
+            say(f"edge m={m} n={n}")
+            a = random_seq(rng, m)
+            b = mutate(rng, a, 0.1)[:n] if n <= m else random_seq(rng, n)
+            check_pair(a, b, P, "edge")
+
+
+def test_single_pair_identical_and_related():
+    rng = np.random.default_rng(22)
+    for L in [1, 100, 777, 1500]:
+        a = random_seq(rng, L)
+        say(f"identical L={L}")
+        s, p = gpu_align(a, a.copy())
+        assert s == L and p.tolist() == [1] * L
+        b = mutate(rng, a, 0.15)
+        check_pair(a, b, P, "related")
+
+
+@pytest.mark.parametrize("sc", [(2, -3, -2), (1, 0, -1), (3, -1, -2), (5, -4, -3), (1, -1, -2)])
+def test_other_scorings(sc):
+    rng = np.random.default_rng(23)
+    for m, n in [(50, 61), (300, 280), (700, 720)]:
+        a = random_seq(rng, m)
+        b = mutate(rng, a, 0.2)[:n]
+        say(f"scoring {sc} m={m} n={len(b)}")
+        check_pair(a, b, sc, "scoring")
+
+
+def test_batch_matches_oracle():
+    pairs = config_batch(seed=31, npairs=300, lo=1, hi=700)
+    pool, ao, al, bo, bl = pack_pairs(pairs)
+    max_len = int(max(al.max(), bl.max()))
+    say(f"batch 300 pairs max_len={max_len}")
+    s_ref, p_ref = oracle.align_batch(pool, ao, al, bo, bl, P)
+    s, paths, plen = gpu_batch(pool, ao, al, bo, bl, max_len, P)
+    assert (s == s_ref).all(), np.nonzero(s != s_ref)
+    for k in range(len(pairs)):
+        assert paths[k].tolist() == p_ref[k].tolist(), k
+    s2, _ = gpu_batch(pool, ao, al, bo, bl, max_len, P, score_only=True)
+    assert (s2 == s_ref).all()
+
+
+def test_batch_pair_beyond_max_len_is_flagged():
+    rng = np.random.default_rng(32)
+    A = [random_seq(rng, 50), random_seq(rng, 120), random_seq(rng, 30)]
+    B = [random_seq(rng, 40), random_seq(rng, 60), random_seq(rng, 30)]
+    pool, off, lens = pack_seqs([x for ab in zip(A, B) for x in ab])
+    ao, bo, al, bl = off[0::2], off[1::2], lens[0::2], lens[1::2]
+    say("batch with an over-long pair")
+    s, paths, plen = gpu_batch(pool, ao, al, bo, bl, 100, P)
+    assert s[1] == np.iinfo(np.int32).min and plen[1] == -1
+    for k in (0, 2):
+        s_ref, p_ref = oracle.align(A[k], B[k], P)
+        assert s[k] == s_ref and paths[k].tolist() == p_ref.tolist()
+
+
+def test_allpairs_matches_oracle():
+    seqs = config_allpairs(seed=41, nseq=40, lo=20, hi=600, root_len=1000)
+    pool, off, lens = pack_seqs(seqs)
+    say("allpairs 40 sequences")
+    M_ref = oracle.allpairs(pool, off, lens, P)
+    M = gpu_allpairs(pool, off, lens, int(lens.max()), P)
+    assert (M == M_ref).all()
+    assert (M == M.T).all() and (np.diag(M) == lens).all()
