@@ -75,6 +75,14 @@ void nw_release_caches(void) {}
 
 static const size_t kDescBytes = 1024;  // one-pair descriptor at the front of ws
 
+static bool use_coop(int64_t m, int64_t n) { return m >= 1 && n >= kCoopMinCols; }
+
+static size_t single_workspace_bytes(int64_t m, int64_t n, bool dirs, const DeviceInfo& di) {
+    if (use_coop(m, n)) return coop_workspace_bytes(m, n, dirs);
+    const int32_t ml = (int32_t)std::max<int64_t>(std::max(m, n), 1);
+    return kDescBytes + batch_workspace_bytes(1, ml, dirs, di);
+}
+
 int nw_align_workspace_size(int64_t m, int64_t n, uint32_t flags, size_t* bytes) {
     if (!bytes || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
     if (m < 0 || n < 0) return NW_EINVAL;
@@ -82,8 +90,7 @@ int nw_align_workspace_size(int64_t m, int64_t n, uint32_t flags, size_t* bytes)
     DeviceInfo di;
     int st = device_info(&di);
     if (st) return st;
-    const int32_t ml = (int32_t)std::max<int64_t>(std::max(m, n), 1);
-    *bytes = kDescBytes + batch_workspace_bytes(1, ml, !(flags & NW_SCORE_ONLY), di);
+    *bytes = single_workspace_bytes(m, n, !(flags & NW_SCORE_ONLY), di);
     return NW_OK;
 }
 
@@ -110,9 +117,11 @@ int nw_align(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, nw_scorin
     if ((st = check_scoring(sc, dirs))) return st;
     DeviceInfo di;
     if ((st = device_info(&di))) return st;
+    if (ws_bytes < single_workspace_bytes(m, n, dirs, di)) return NW_ENOSPC;
+    if (use_coop(m, n))
+        return launch_coop(a, m, b, n, sc, dirs, score, path, path_len, ws, ws_bytes,
+                           (hipStream_t)stream, di);
     const int32_t ml = (int32_t)std::max<int64_t>(std::max(m, n), 1);
-    const size_t need = kDescBytes + batch_workspace_bytes(1, ml, dirs, di);
-    if (ws_bytes < need) return NW_ENOSPC;
 
     uint8_t* base = (uint8_t*)ws;
     int64_t* d64 = (int64_t*)base;

@@ -183,9 +183,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
             for (int s = 0; s < nstrips; ++s) {
                 const int j0 = s * kCols;
                 const int ksel = (n - 1 - j0) % C;
-                vlast = sweep_strip<C, DIRS>(P.a, m, P.b, n, j0, A.kdm, A.kdx, vinit,
-                                             s == 0 ? nullptr : bnd,
-                                             s == nstrips - 1 ? nullptr : bnd,
+                const PlainIO io{s == 0 ? nullptr : bnd, s == nstrips - 1 ? nullptr : bnd, m, vinit};
+                vlast = sweep_strip<C, DIRS>(P.a, m, P.b, n, j0, A.kdm, A.kdx, vinit, io,
                                              DIRS ? dirs + (size_t)s * G * kWave * C : nullptr,
                                              lds, ksel);
                 fence_wave_memory();

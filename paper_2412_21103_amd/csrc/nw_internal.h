@@ -50,6 +50,14 @@ struct BatchJob {
     int32_t* matrix;     // all-pairs mode
 };
 
+// Cooperative single-pair engine (nw_single.hip): used for one pair with at
+// least kCoopMinCols columns.
+constexpr int64_t kCoopMinCols = 512;
+size_t coop_workspace_bytes(int64_t m, int64_t n, bool dirs);
+int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const nw_scoring& sc,
+                bool dirs, int32_t* score, uint8_t* path, int64_t* path_len, void* ws,
+                size_t ws_bytes, hipStream_t stream, const DeviceInfo& di);
+
 size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di);
 int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t stream,
                  const DeviceInfo& di);

@@ -7,11 +7,18 @@
 // previous step, the horizontal input of column k > 0 is the value just
 // produced for column k-1, and the horizontal input of column 0 is the
 // previous step's last-column value of lane l-1, moved across lanes with one
-// DPP wave shift.  Lane 0 takes that value from a 64-entry queue register R:
-// R is shifted left one lane per step, so lane 0 consumes the next row's
+// DPP wave shift.  Lane 0 takes that value from a queue register R: R is
+// shifted left one lane per step, so lane 0 consumes the next row's
 // left-boundary value while lane 63 appends its own last-column value, which
 // is the strip's right boundary for the next strip.  Every 16 steps lanes
-// 48..63 of R are written out and refilled.
+// 48..63 (the last 16 outputs) are written out and lanes 0..15 are refilled
+// with the next 16 inputs; whatever sits in lanes 16..47 reaches lane 0 only
+// after the next refill has overwritten it, so inputs are needed just one
+// group (16 rows) ahead.
+//
+// Boundary columns travel through an IO policy: PlainIO for a wave that
+// sweeps all strips of a pair itself, TaggedIO when neighbouring strips run
+// on different waves (see the cooperative kernel).
 //
 // The substitution term comes from a per-row table in LDS: for row i the word
 // holds four signed bytes, byte y = term(a_i == y).  Lane (l, k) reads byte
@@ -59,20 +66,91 @@ __device__ __forceinline__ void write_window(uint32_t* win, const uint8_t* a, in
     }
 }
 
-// Boundary input for row r: from bin (previous strip's right column) or the
-// first column of the grid; rows beyond m get 0, which never wins.
-__device__ __forceinline__ int32_t boundary_in(const int32_t* bin, int r, int m, int32_t vinit) {
-    if (r > m) return 0;
-    return bin ? bin[r] : vinit;
+// Boundary IO for a wave that owns every strip of its pair: the previous
+// strip's right column sits in the wave's own scratch (bin), the next strip's
+// goes to the same buffer (bout; reads of a row happen before its overwrite).
+// Rows beyond m read 0, which never wins; a missing bin means the grid's
+// first column (vinit).
+struct PlainIO {
+    const int32_t* bin;
+    int32_t* bout;
+    int m;
+    int32_t vinit;
+    using Slot = int32_t;
+    __device__ __forceinline__ Slot load(int r, bool want) const {
+        return (want && bin && r <= m) ? bin[r] : 0;
+    }
+    __device__ __forceinline__ int32_t value(Slot x, int r) const {
+        return r > m ? 0 : (bin ? x : vinit);
+    }
+    __device__ __forceinline__ bool ready(Slot, int, bool) const { return true; }
+    __device__ __forceinline__ void store(int r, int32_t v, bool want) const {
+        if (bout && want) bout[r] = v;
+    }
+    __device__ __forceinline__ void fail() const {}
+    __device__ __forceinline__ bool failed() const { return false; }
+};
+
+// Boundary IO between strips swept by different waves, possibly on different
+// CUs or XCDs.  Each row slot is 64 bits, {value, epoch}, written with one
+// device-coherent atomic store; the reader polls the slot until it carries the
+// current call's epoch, so no separate flag (and no cache write-back) is
+// needed.  Polling gives up after a bounded number of rounds and raises *err.
+struct TaggedIO {
+    const uint64_t* bin;
+    uint64_t* bout;
+    int m;
+    int32_t vinit;
+    uint32_t epoch;
+    int32_t* err;
+    using Slot = uint64_t;
+    __device__ __forceinline__ Slot load(int r, bool want) const {
+        if (!(want && bin && r <= m)) return 0;
+        return __hip_atomic_load(bin + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ int32_t value(Slot x, int r) const {
+        return r > m ? 0 : (bin ? (int32_t)(uint32_t)x : vinit);
+    }
+    __device__ __forceinline__ bool ready(Slot x, int r, bool want) const {
+        return !(want && bin && r <= m) || (uint32_t)(x >> 32) == epoch;
+    }
+    __device__ __forceinline__ void store(int r, int32_t v, bool want) const {
+        if (bout && want)
+            __hip_atomic_store(bout + r, ((uint64_t)epoch << 32) | (uint32_t)v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ void fail() const {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ bool failed() const {
+        return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    }
+};
+
+constexpr int kSpinLimit = 1 << 16;  // polling rounds before a boundary wait gives up
+
+// Load slot r (for the lanes with `want`) until every such lane sees a ready
+// slot.  The loop condition is wave-uniform.
+template <class IO>
+__device__ __forceinline__ typename IO::Slot wait_slot(const IO& io, int r, bool want) {
+    typename IO::Slot x = io.load(r, want);
+    for (int spin = 0; spin < kSpinLimit; ++spin) {
+        if (__builtin_amdgcn_ballot_w64(!io.ready(x, r, want)) == 0) return x;
+        if (io.failed()) return x;  // another wait already gave up: drain quickly
+        __builtin_amdgcn_s_sleep(2);
+        x = io.load(r, want);
+    }
+    io.fail();
+    return x;
 }
 
 // Sweep one strip.  Returns, per lane, V (or W) of its column `ksel` after
 // the last row (the frozen final value).
-template <int C, bool DIRS>
-__device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, int m, const uint8_t* __restrict__ b,
-                               int n, int j0, int kdm, int kdx, int32_t vinit,
-                               const int32_t* bin, int32_t* bout, uint32_t* __restrict__ dirs,
-                               uint32_t* lds, int ksel) {
+template <int C, bool DIRS, class IO>
+__device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, int m,
+                                               const uint8_t* __restrict__ b, int n, int j0, int kdm,
+                                               int kdx, int32_t vinit, const IO& io,
+                                               uint32_t* __restrict__ dirs, uint32_t* lds, int ksel) {
     const int lane = lane_id();
     int32_t V[C];
     uint32_t acc[C];
@@ -85,7 +163,7 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
         bcode[k] = (j < n) ? (uint32_t)(b[j] & 3) : 0u;
     }
     int32_t Dg = vinit;
-    int32_t R = boundary_in(bin, lane + 1, m, vinit);
+    int32_t R = io.value(wait_slot(io, lane + 1, lane < 16), lane + 1);
 
     const int NG = groups_for_rows(m);
     // window 0 covers groups [0, 8): rows [-63, 129)
@@ -128,33 +206,54 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
 #pragma unroll
         for (int k = 0; k < C; ++k) addr[k] = (base + bcode[k]) & 0x7FFFu;
 
-        // boundary values for the refill at the end of this group
+        // boundary values for the refill of lanes 0..15 at the end of this group
         const int rin = 16 * (g + 1) + 1 + lane;
-        const int32_t Rin = (bin && lane >= 48 && rin <= m) ? bin[rin] : (rin <= m ? vinit : 0);
+        typename IO::Slot Rin = io.load(rin, lane < 16);
+
+        // Narrow strips have too little work per step to hide the LDS latency
+        // behind other waves, so their whole group of table reads is issued up
+        // front; wide strips read one step at a time.
+        constexpr bool kHoist = (C <= 2);
+        int32_t kdh[kHoist ? 16 : 1][C];
+        if constexpr (kHoist) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+#pragma unroll
+                for (int k = 0; k < C; ++k) kdh[u][k] = (int32_t)lds8[addr[k] + 4 * u];
+        }
 
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            int32_t Lr = dpp_from_left(R, V[C - 1]);
-            R = dpp_from_right(V[C - 1], R);
+            const int32_t Lr = dpp_from_left(R, V[C - 1]);
             int32_t left = Lr;
             int32_t diag = Dg;
+            int32_t tail = 0;  // the last column's previous value (+1 in the V domain)
 #pragma unroll
             for (int k = 0; k < C; ++k) {
-                int32_t kd = (int32_t)lds8[addr[k] + 4 * u];
-                int32_t up = V[k];
-                int32_t cD = diag + kd;
+                int32_t kd;
+                if constexpr (kHoist) kd = kdh[u][k];
+                else kd = (int32_t)lds8[addr[k] + 4 * u];
+                const int32_t up = V[k];
+                const int32_t cD = diag + kd;
                 int32_t v;
                 if constexpr (DIRS) {
-                    int32_t r = imax3(cD, up + 1, left);
+                    const int32_t cU = up + 1;
+                    const int32_t r = imax3(cD, cU, left);
                     acc[k] = shift_in_tag((uint32_t)r, acc[k]);
                     v = clear_tag(r);
+                    if (k == C - 1) tail = cU;
                 } else {
                     v = imax3(cD, up, left);
+                    if (k == C - 1) tail = up;
                 }
                 diag = up;
                 V[k] = v;
                 left = v;
             }
+            // lane 63 appends its last column's value of the previous step; in the
+            // V domain that value is taken as cU = V + 1, whose register is free
+            // now, and the 1 comes off when the group's outputs are stored
+            R = dpp_from_right(tail, R);
             Dg = Lr;
         }
         if constexpr (DIRS) {
@@ -164,8 +263,10 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
         }
         {
             const int r = 16 * g + lane - 111;
-            if (bout && lane >= 48 && r >= 1 && r <= m) bout[r] = R;
-            R = (lane >= 48) ? Rin : R;
+            io.store(r, DIRS ? R - 1 : R, lane >= 48 && r >= 1 && r <= m);
+            if (__builtin_amdgcn_ballot_w64(!io.ready(Rin, rin, lane < 16)) != 0)
+                Rin = wait_slot(io, rin, lane < 16);
+            R = (lane < 16) ? io.value(Rin, rin) : R;
         }
     }
     int32_t out = V[0];

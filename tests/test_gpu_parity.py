@@ -101,3 +101,31 @@ def test_allpairs_matches_oracle():
     M = gpu_allpairs(pool, off, lens, int(lens.max()), P)
     assert (M == M_ref).all()
     assert (M == M.T).all() and (np.diag(M) == lens).all()
+
+
+def test_cooperative_single_pair_shapes():
+    # one pair with n >= 512 runs on many waves; cover tiny m, strip-multiple
+    # and ragged n, and long m
+    rng = np.random.default_rng(24)
+    for m, n in [(1, 512), (2, 4096), (17, 640), (100, 5000), (3000, 2999), (4097, 4096),
+                 (700, 8193), (9000, 1100)]:
+        a = random_seq(rng, m)
+        b = mutate(rng, random_seq(rng, n), 0.0) if m < 50 else mutate(rng, a, 0.12)[:n]
+        if len(b) < n:
+            b = np.concatenate([b, random_seq(rng, n - len(b))])
+        say(f"coop m={m} n={n}")
+        check_pair(a, b, P, "coop")
+
+
+def test_long_pair_full_size():
+    from workloads import config_long_pair
+    p = config_long_pair()
+    a, b = p.a[0], p.b[0]
+    say(f"long pair {len(a)} x {len(b)}: GPU")
+    s, path = gpu_align(a, b)
+    say("long pair: oracle (two-row mode)")
+    s_ref, p_ref = oracle.align(a, b, P, full_limit_bytes=0)
+    assert s == s_ref
+    assert path.tolist() == p_ref.tolist()
+    r, ok = oracle.rescore(path, a, b, P)
+    assert ok and r == s
