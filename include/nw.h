@@ -135,6 +135,24 @@ int nw_allpairs_scores(int32_t nseq, const uint8_t *pool, const int64_t *off,
  * no library call is in flight. */
 void nw_release_caches(void);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing for benchmarks.  Between nw_profile_begin() and
+ * nw_profile_end() the library records a HIP event before and after every
+ * kernel it launches, on that call's stream.  Call nw_profile_end() only
+ * after those streams have been synchronised: it writes up to `cap` records
+ * (one per kernel name: launch count and summed milliseconds) to out (host
+ * memory), the number of distinct kernels to *count (host), and stops
+ * recording.  Not thread-safe; meant for single-threaded benchmark drivers.
+ * ------------------------------------------------------------------------ */
+typedef struct nw_kernel_time {
+    const char *name;   /* static storage */
+    int32_t launches;
+    double total_ms;
+} nw_kernel_time;
+
+int nw_profile_begin(void);
+int nw_profile_end(nw_kernel_time *out, int32_t cap, int32_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,8 @@ import torch
 __all__ = [
     "Scoring", "NWError", "PAPER_SCORING", "lib", "align", "align_batch", "allpairs",
     "align_workspace_size", "batch_workspace_size", "allpairs_workspace_size",
-    "declared_functions", "MOVE_D", "MOVE_U", "MOVE_L", "SCORE_ONLY",
+    "declared_functions", "MOVE_D", "MOVE_U", "MOVE_L", "SCORE_ONLY", "profile_begin",
+    "profile_end",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,6 +34,10 @@ NW_OK, NW_EINVAL, NW_ERANGE, NW_ENOSPC, NW_EDEVICE, NW_ENOTSUP = 0, -1, -2, -3, 
 
 class Scoring(ctypes.Structure):
     _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32), ("gap", ctypes.c_int32)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double)]
 
 
 class NWError(RuntimeError):
@@ -66,6 +71,8 @@ def lib():
         L.nw_allpairs_workspace_size.argtypes = [_i32, _i32, ctypes.POINTER(_sz)]
         L.nw_allpairs_scores.argtypes = [_i32, _vp, _vp, _vp, _i32, Scoring, _vp, _vp, _sz, _vp]
         L.nw_release_caches.restype = None
+        L.nw_profile_begin.restype = ctypes.c_int
+        L.nw_profile_end.argtypes = [ctypes.POINTER(KernelTime), _i32, ctypes.POINTER(_i32)]
         _lib = L
     return _lib
 
@@ -186,3 +193,18 @@ def allpairs(pool: torch.Tensor, off: torch.Tensor, lens: torch.Tensor, max_len:
                                   _ptr(out), _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "nw_allpairs_scores")
     return out
+
+
+def profile_begin():
+    """Start recording HIP events around every library kernel launch."""
+    _check(lib().nw_profile_begin(), "nw_profile_begin")
+
+
+def profile_end():
+    """Stop recording; call after synchronising.  Returns {kernel: (launches, total_ms)}."""
+    cap = 64
+    buf = (KernelTime * cap)()
+    cnt = _i32(0)
+    _check(lib().nw_profile_end(buf, cap, ctypes.byref(cnt)), "nw_profile_end")
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
+            for i in range(min(cnt.value, cap))}

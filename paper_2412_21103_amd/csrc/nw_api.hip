@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 #include "nw_internal.h"
 
@@ -49,6 +51,48 @@ static int check_lengths(int64_t m, int64_t n, const nw_scoring& sc) {
     return NW_OK;
 }
 
+// ---- optional kernel timing ----
+
+namespace {
+struct ProfState {
+    bool on = false;
+    std::vector<hipEvent_t> pool;  // events, reused across sessions
+    size_t used = 0;
+    std::vector<std::pair<const char*, int>> marks;  // (name, index of start event)
+};
+ProfState& prof() {
+    static ProfState s;
+    return s;
+}
+hipEvent_t prof_event() {
+    ProfState& P = prof();
+    if (P.used == P.pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        P.pool.push_back(e);
+    }
+    return P.pool[P.used++];
+}
+}  // namespace
+
+ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), st(s), slot(-1) {
+    ProfState& P = prof();
+    if (!P.on) return;
+    hipEvent_t e = prof_event();
+    if (!e) return;
+    slot = (int)P.used - 1;
+    (void)hipEventRecord(e, st);
+}
+
+ProfScope::~ProfScope() {
+    if (slot < 0) return;
+    ProfState& P = prof();
+    hipEvent_t e = prof_event();
+    if (!e) return;
+    (void)hipEventRecord(e, st);
+    P.marks.emplace_back(name, slot);
+}
+
 }  // namespace nw
 
 using namespace nw;
@@ -70,6 +114,36 @@ const char* nw_strerror(int status) {
 int nw_version(void) { return 100; }
 
 void nw_release_caches(void) {}
+
+int nw_profile_begin(void) {
+    ProfState& P = prof();
+    P.on = true;
+    P.used = 0;
+    P.marks.clear();
+    return NW_OK;
+}
+
+int nw_profile_end(nw_kernel_time* out, int32_t cap, int32_t* count) {
+    ProfState& P = prof();
+    P.on = false;
+    if (!count || (cap > 0 && !out)) return NW_EINVAL;
+    std::vector<nw_kernel_time> acc;
+    for (auto& mk : P.marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, P.pool[mk.second], P.pool[mk.second + 1]) != hipSuccess)
+            return NW_EDEVICE;
+        size_t i = 0;
+        while (i < acc.size() && std::strcmp(acc[i].name, mk.first) != 0) ++i;
+        if (i == acc.size()) acc.push_back(nw_kernel_time{mk.first, 0, 0.0});
+        acc[i].launches += 1;
+        acc[i].total_ms += ms;
+    }
+    *count = (int32_t)acc.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)acc.size(); ++i) out[i] = acc[i];
+    P.marks.clear();
+    P.used = 0;
+    return NW_OK;
+}
 
 // ---------------------------------------------------------------- one pair
 

@@ -264,6 +264,7 @@ size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const De
 
 template <int C, bool DIRS, bool ALLPAIRS>
 static void launch_engine(const KArgs& A, int64_t grid, hipStream_t st) {
+    ProfScope ps(ALLPAIRS ? "nw_allpairs" : (DIRS ? "nw_batch" : "nw_batch_score"), st);
     hipLaunchKernelGGL((k_batch<C, DIRS, ALLPAIRS>), dim3((unsigned)grid), dim3(kBlockThreads), 0, st, A);
 }
 

@@ -28,6 +28,17 @@ int device_info(DeviceInfo* out);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Optional per-kernel timing (nw_profile_begin / nw_profile_end).  Construct
+// a ProfScope right before a launch and let it go out of scope right after:
+// while profiling is on it records a HIP event pair on the launch's stream.
+struct ProfScope {
+    ProfScope(const char* name, hipStream_t st);
+    ~ProfScope();
+    const char* name;
+    hipStream_t st;
+    int slot;
+};
+
 // Persistent batch engine (nw_batch.hip).
 struct BatchJob {
     // pairs: explicit arrays; all-pairs: nseq sequences, jobs are i <= j

@@ -162,7 +162,10 @@ static hipError_t launch_coop_kernel(const CoopArgs& A, int grid, hipStream_t st
         if (e != hipSuccess) return e;
         configured = true;
     }
-    hipLaunchKernelGGL((k_coop<kCoopC, DIRS>), dim3(grid), dim3(kCoopThreads), kCoopDynLds, st, A);
+    {
+        ProfScope ps(DIRS ? "nw_fill_coop" : "nw_fill_coop_score", st);
+        hipLaunchKernelGGL((k_coop<kCoopC, DIRS>), dim3(grid), dim3(kCoopThreads), kCoopDynLds, st, A);
+    }
     return hipGetLastError();
 }
 
@@ -207,6 +210,7 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
         W.path_len = path_len;
         W.score = score;
         W.err = A.err;
+        ProfScope ps("nw_walk_single", st);
         hipLaunchKernelGGL(k_walk<kCoopC>, dim3(1), dim3(kWave), 0, st, W);
     }
     return hipGetLastError() == hipSuccess ? NW_OK : NW_EDEVICE;
