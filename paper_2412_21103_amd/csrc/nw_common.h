@@ -38,6 +38,14 @@ __device__ __forceinline__ int32_t dpp_from_left(int32_t old, int32_t src) {
     return __builtin_amdgcn_update_dpp(old, src, kDppWaveShr1, 0xF, 0xF, false);
 }
 
+// Lane 0 takes `first`; lanes 1..63 take src of lane-1.  Written as a
+// zero-filled DPP shift and a lane-0 select so the compiler can fold both into
+// one v_cndmask_b32 with a DPP source (no copy of `first` is needed).
+__device__ __forceinline__ int32_t shift_in_from_left(int32_t first, int32_t src, bool lane0) {
+    const int32_t sh = __builtin_amdgcn_update_dpp(0, src, kDppWaveShr1, 0xF, 0xF, true);
+    return lane0 ? first : sh;
+}
+
 __device__ __forceinline__ int32_t dpp_from_right(int32_t old, int32_t src) {
     // lanes 0..62 take src of lane+1; lane 63 keeps old
     return __builtin_amdgcn_update_dpp(old, src, kDppWaveShl1, 0xF, 0xF, false);

@@ -10,8 +10,18 @@
 // the fill runs as one anti-diagonal front across all strips, each strip a
 // fixed lag behind its left neighbour.
 //
-// The traceback then walks the stored direction words from (m, n) with one
-// wave (walk_back), and writes the path in forward order.
+// Traceback.  A single serial walk from (m, n) would take one dependent
+// lookup per move (about 130k moves for a 65,536-base pair).  Instead every
+// strip first walks its own part of the path in parallel (k_tb_spec), starting
+// from a guessed entry row: the row near the diagonal where the strip's right
+// boundary column (left behind by the fill) scores best.  The strip notes, for each of its
+// columns, the rows its walk visited and the move index at which it entered
+// the column.  One wave then chains the strips from the last to the first
+// (k_tb_fix): the true path enters strip s where it left strip s+1; if that
+// cell lies on strip s's walk, the rest of the strip is that walk's suffix
+// (walks from the same cell are identical), otherwise the wave walks from the
+// true entry until it meets the speculative walk or leaves the strip.  A last
+// pass (k_tb_emit) writes every strip's segment, reversed, at its offset.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -66,7 +76,9 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
                               A.m,
                               A.vinit,
                               A.epoch,
-                              A.err};
+                              A.err,
+                              wave > 0,
+                              wave < kCoopWaves - 1};
             const int32_t v = sweep_strip<C, DIRS>(A.a, A.m, A.b, A.n, j0, A.kdm, A.kdx, A.vinit, io,
                                                    DIRS ? A.dirs + (size_t)s * A.G * kWave * C : nullptr,
                                                    lds, ksel);
@@ -79,37 +91,287 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
     }
 }
 
-struct WalkArgs {
+// Score-only calls: report a boundary-wait failure of the fill as INT32_MIN.
+__global__ void k_check_fill(const int32_t* err, int32_t* score) {
+    if (threadIdx.x == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+        score[0] = INT32_MIN;
+}
+
+// ---- parallel traceback over strips ----
+
+constexpr int kInfoHead = 8;  // len, start_row, exit_row, lo/hi of the entry column, pad
+constexpr int kGuessSpan = 4096;  // rows searched on each side of the diagonal for an entry guess
+
+struct TbArgs {
     const uint32_t* dirs;
-    int m, n, G;
-    uint8_t* rev;
+    int m, n, G, nstrips;
+    const uint64_t* bnd;  // right boundary column of every strip but the last
+    int64_t bnd_stride;
+    int32_t key_gap;      // 4 * gap: V + key_gap * i orders a column's rows like H
+    uint8_t* seg;        // per strip: speculative moves, backward order
+    uint8_t* rw;         // per strip: re-walk moves, backward order
+    int64_t seg_stride;
+    int32_t* info;       // per strip: kInfoHead ints, then lo[], hi[], idx[] per column
+    int64_t info_stride;
+    int32_t* fix;        // per strip: rw_len, seg_from, total_len, offset
+    int32_t* summary;    // [0] tail (vertical moves at column 0), [1] path length, [2] error
+    const int32_t* err;  // fill failure flag
     uint8_t* path;
     int64_t* path_len;
     int32_t* score;
-    const int32_t* err;
+    int64_t cap;         // path capacity, m + n
 };
 
-// Traceback of the cooperative fill (also reports a boundary-wait failure of
-// the fill as score INT32_MIN and path length -3).
 template <int C>
-__global__ __launch_bounds__(kWave) void k_walk(WalkArgs W) {
-    __shared__ uint32_t lds[kWave * C];
+__global__ __launch_bounds__(kCoopThreads) void k_tb_spec(TbArgs T) {
+    constexpr int kCols = kWave * C;
+    __shared__ uint32_t win_lds[kCoopWaves][kWave * C];
+    __shared__ int32_t col_lds[kCoopWaves][3][kCols];
+    const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
-    if (__hip_atomic_load(W.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        W.score[0] = INT32_MIN;
-        if (W.path_len) W.path_len[0] = -3;
+    const int s = blockIdx.x * kCoopWaves + wave;
+    if (s >= T.nstrips) return;
+    if (__hip_atomic_load(T.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    const int j_lo = s * kCols + 1;
+    const int j_hi = min((s + 1) * kCols, T.n);
+    int i = T.m, j = T.n;
+    if (s < T.nstrips - 1) {
+        // Entry guess: the row where the strip's right boundary column scores
+        // best, searched within kGuessSpan rows of the proportional diagonal.
+        const int64_t c = ((int64_t)j_hi * T.m + T.n / 2) / T.n;
+        const int r0 = (int)max<int64_t>(1, c - kGuessSpan), r1 = (int)min<int64_t>(T.m, c + kGuessSpan);
+        const uint64_t* col = T.bnd + (int64_t)s * T.bnd_stride;
+        int32_t best_key = INT32_MIN, best_row = r0;
+        for (int r = r0 + lane; r <= r1; r += kWave) {
+            const int32_t key = (int32_t)(uint32_t)col[r] + T.key_gap * r;
+            if (key > best_key) {
+                best_key = key;
+                best_row = r;
+            }
+        }
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int32_t ok = __shfl_xor(best_key, d);
+            const int32_t orow = __shfl_xor(best_row, d);
+            if (ok > best_key || (ok == best_key && orow < best_row)) {
+                best_key = ok;
+                best_row = orow;
+            }
+        }
+        i = uniform(best_row);
+        j = j_hi;
+    }
+    const int start_row = i;
+    int32_t* lo = col_lds[wave][0];
+    int32_t* hi = col_lds[wave][1];
+    int32_t* idx = col_lds[wave][2];
+    for (int c = lane; c < kCols; c += kWave) {
+        lo[c] = -1;
+        hi[c] = -1;
+        idx[c] = -1;
+    }
+    __builtin_amdgcn_wave_barrier();
+    DirWindow<C> win(T.dirs, T.G, win_lds[wave]);
+    uint8_t* out = T.seg + (int64_t)s * T.seg_stride;
+    int q = 0, cur = -1;
+    bool bad = false;
+    while (j >= j_lo) {
+        const int c = j - j_lo;
+        if (c != cur) {
+            hi[c] = i;
+            idx[c] = q;
+            cur = c;
+        }
+        lo[c] = i;
+        int mv = 3;
+        if (i > 0) {
+            const int tag = win.tag(i, j);
+            if (tag == 0) {
+                bad = true;
+                break;
+            }
+            mv = 4 - tag;
+        }
+        out[q++] = (uint8_t)mv;
+        if (mv == 1) {
+            --i;
+            --j;
+        } else if (mv == 2) {
+            --i;
+        } else {
+            --j;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    int32_t* rec = T.info + (int64_t)s * T.info_stride;
+    const int cR = j_hi - j_lo;
+    if (lane == 0) {
+        rec[0] = q;
+        rec[1] = start_row;
+        rec[2] = i;
+        rec[3] = lo[cR];
+        rec[4] = hi[cR];
+        rec[5] = bad ? 1 : 0;
+    }
+    for (int c = lane; c < kCols; c += kWave) {
+        rec[kInfoHead + c] = lo[c];
+        rec[kInfoHead + kCols + c] = hi[c];
+        rec[kInfoHead + 2 * kCols + c] = idx[c];
+    }
+}
+
+// One wave chains the strips from the last to the first.
+template <int C>
+__global__ __launch_bounds__(kWave) void k_tb_fix(TbArgs T) {
+    constexpr int kCols = kWave * C;
+    __shared__ uint32_t win_lds[kWave * C];
+    __shared__ int32_t col_lds[3][kCols];
+    const int lane = lane_id();
+    if (__hip_atomic_load(T.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if (lane == 0) T.summary[2] = 3;
         return;
     }
-    if (!W.dirs) return;
-    const int64_t len = walk_back<C>(W.dirs, W.m, W.n, W.G, lds, W.rev);
+    DirWindow<C> win(T.dirs, T.G, win_lds);
+    int e = T.m;     // entry row of the current strip
+    int error = 0;
+    // headers arrive 64 strips at a time: lane q holds strip (base - q)
+    int base = T.nstrips - 1;
+    int32_t h_len = 0, h_start = 0, h_exit = 0, h_lo = 0, h_hi = 0, h_bad = 0;
+    auto load_chunk = [&](int b) {
+        const int sq = b - lane;
+        if (sq >= 0) {
+            const int32_t* rec = T.info + (int64_t)sq * T.info_stride;
+            h_len = rec[0];
+            h_start = rec[1];
+            h_exit = rec[2];
+            h_lo = rec[3];
+            h_hi = rec[4];
+            h_bad = rec[5];
+        }
+    };
+    load_chunk(base);
+    for (int s = T.nstrips - 1; s >= 0; --s) {
+        if (base - s >= kWave) {
+            base = s;
+            load_chunk(base);
+        }
+        const int ql = base - s;
+        const int len = __builtin_amdgcn_readlane(h_len, ql);
+        const int start = __builtin_amdgcn_readlane(h_start, ql);
+        const int sexit = __builtin_amdgcn_readlane(h_exit, ql);
+        const int loR = __builtin_amdgcn_readlane(h_lo, ql);
+        const int hiR = __builtin_amdgcn_readlane(h_hi, ql);
+        error |= __builtin_amdgcn_readlane(h_bad, ql);
+        int rw_len = 0, seg_from = 0, exit_row = sexit;
+        if (s == T.nstrips - 1) {
+            seg_from = 0;
+        } else if (hiR >= 0 && loR <= e && e <= hiR) {
+            seg_from = start - e;
+        } else {
+            // walk from the true entry until the speculative walk is met
+            const int j_lo = s * kCols + 1;
+            const int32_t* rec = T.info + (int64_t)s * T.info_stride + kInfoHead;
+            for (int c = lane; c < kCols; c += kWave) {
+                col_lds[0][c] = rec[c];
+                col_lds[1][c] = rec[kCols + c];
+                col_lds[2][c] = rec[2 * kCols + c];
+            }
+            __builtin_amdgcn_wave_barrier();
+            uint8_t* out = T.rw + (int64_t)s * T.seg_stride;
+            int i = e, j = min((s + 1) * kCols, T.n);
+            bool merged = false;
+            while (j >= j_lo) {
+                const int c = j - j_lo;
+                const int clo = col_lds[0][c], chi = col_lds[1][c];
+                if (chi >= 0 && clo <= i && i <= chi) {
+                    seg_from = col_lds[2][c] + (chi - i);
+                    merged = true;
+                    break;
+                }
+                int mv = 3;
+                if (i > 0) {
+                    const int tag = win.tag(i, j);
+                    if (tag == 0) {
+                        error = 1;
+                        break;
+                    }
+                    mv = 4 - tag;
+                }
+                out[rw_len++] = (uint8_t)mv;
+                if (mv == 1) {
+                    --i;
+                    --j;
+                } else if (mv == 2) {
+                    --i;
+                } else {
+                    --j;
+                }
+            }
+            if (!merged) {
+                seg_from = len;
+                exit_row = i;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        int32_t* f = T.fix + 4 * (int64_t)s;
+        f[0] = rw_len;
+        f[1] = seg_from;
+        f[2] = rw_len + (len - seg_from);
+        e = exit_row;
+    }
+    // e is now the row at which the path reaches column 0: that many vertical
+    // moves come first in forward order, then strips 0, 1, ... in turn
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (len < 0) {
-        W.path_len[0] = -2;
+    int64_t off = e;
+    for (int b = 0; b < T.nstrips; b += kWave) {
+        const int sq = b + lane;
+        const int32_t tl = (sq < T.nstrips) ? T.fix[4 * (int64_t)sq + 2] : 0;
+        // inclusive prefix sum across the wave
+        int32_t x = tl;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int32_t y = __shfl_up(x, d);
+            if (lane >= d) x += y;
+        }
+        if (sq < T.nstrips) T.fix[4 * (int64_t)sq + 3] = (int32_t)(off + x - tl);
+        off += __builtin_amdgcn_readlane(x, kWave - 1);
+    }
+    if (off > T.cap || off < 0) error = 1;  // never expected: a consistent path has <= m + n moves
+    if (lane == 0) {
+        T.summary[0] = 0;
+        T.summary[1] = (int32_t)off;
+        T.summary[2] = error;
+        T.summary[3] = e;
+    }
+}
+
+template <int C>
+__global__ __launch_bounds__(kCoopThreads) void k_tb_emit(TbArgs T) {
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int s = blockIdx.x * kCoopWaves + wave;
+    if (T.summary[2] != 0) {
+        if (s == 0 && lane == 0) {
+            T.score[0] = INT32_MIN;
+            T.path_len[0] = T.summary[2] == 3 ? -3 : -2;
+        }
         return;
     }
-    for (int64_t x = lane; x < len; x += kWave) W.path[x] = W.rev[len - 1 - x];
-    W.path_len[0] = len;
+    if (s == 0) {
+        const int tail = T.summary[3];
+        for (int x = lane; x < tail; x += kWave) T.path[x] = 2;
+        if (lane == 0) T.path_len[0] = T.summary[1];
+    }
+    if (s >= T.nstrips) return;
+    const int32_t* f = T.fix + 4 * (int64_t)s;
+    const int rw_len = f[0], seg_from = f[1], L = f[2], o = f[3];
+    const uint8_t* rw = T.rw + (int64_t)s * T.seg_stride;
+    const uint8_t* sg = T.seg + (int64_t)s * T.seg_stride + seg_from - rw_len;
+    for (int x = lane; x < L; x += kWave) {
+        const int y = L - 1 - x;
+        if ((int64_t)o + x < T.cap) T.path[o + x] = (y < rw_len) ? rw[y] : sg[y];
+    }
 }
 
 __global__ void k_zero_small(int32_t* p, int n) {
@@ -123,10 +385,12 @@ constexpr int kCoopC = 1;
 
 struct CoopLayout {
     int nstrips, ngroups, G;
-    int64_t bnd_stride;
-    size_t off_bnd, off_dirs, off_rev, total;
+    int64_t bnd_stride, seg_stride, info_stride;
+    size_t off_bnd, off_dirs, off_info, off_fix, off_seg, off_rw, total;
 };
 
+// Workspace: [ticket, err, summary | boundary slots | directions |
+// per-strip walk records | per-strip fix-up records | walk moves | re-walk moves]
 static CoopLayout coop_layout(int64_t m, int64_t n, bool dirs) {
     CoopLayout L{};
     const int64_t cols = (int64_t)kWave * kCoopC;
@@ -134,13 +398,24 @@ static CoopLayout coop_layout(int64_t m, int64_t n, bool dirs) {
     L.ngroups = (L.nstrips + kCoopWaves - 1) / kCoopWaves;
     L.G = groups_for_rows((int)m);
     L.bnd_stride = (int64_t)align_up((size_t)(m + 1), 32);
+    L.seg_stride = (int64_t)align_up((size_t)(m + cols + 16), 64);
+    L.info_stride = kInfoHead + 3 * cols;
+    const size_t ns = (size_t)L.nstrips;
     size_t off = 256;
     L.off_bnd = off;
     off = align_up(off + (size_t)std::max(L.nstrips - 1, 0) * L.bnd_stride * 8, 256);
     L.off_dirs = off;
-    if (dirs) off = align_up(off + (size_t)L.nstrips * L.G * kWave * kCoopC * 4, 256);
-    L.off_rev = off;
-    if (dirs) off = align_up(off + (size_t)(m + n + 16), 256);
+    if (dirs) {
+        off = align_up(off + ns * L.G * kWave * kCoopC * 4, 256);
+        L.off_info = off;
+        off = align_up(off + ns * L.info_stride * 4, 256);
+        L.off_fix = off;
+        off = align_up(off + ns * 16, 256);
+        L.off_seg = off;
+        off = align_up(off + ns * L.seg_stride, 256);
+        L.off_rw = off;
+        off = align_up(off + ns * L.seg_stride, 256);
+    }
     L.total = off;
     return L;
 }
@@ -199,19 +474,43 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
     const int grid = std::max(1, std::min(L.ngroups, di.cus));
     hipError_t e = dirs ? launch_coop_kernel<true>(A, grid, st) : launch_coop_kernel<false>(A, grid, st);
     if (e != hipSuccess) return NW_EDEVICE;
-    {
-        WalkArgs W{};
-        W.dirs = A.dirs;
-        W.m = (int)m;
-        W.n = (int)n;
-        W.G = L.G;
-        W.rev = base + L.off_rev;
-        W.path = path;
-        W.path_len = path_len;
-        W.score = score;
-        W.err = A.err;
-        ProfScope ps("nw_walk_single", st);
-        hipLaunchKernelGGL(k_walk<kCoopC>, dim3(1), dim3(kWave), 0, st, W);
+    if (!dirs) {
+        hipLaunchKernelGGL(k_check_fill, dim3(1), dim3(64), 0, st, A.err, score);
+    } else {
+        TbArgs T{};
+        T.dirs = A.dirs;
+        T.m = (int)m;
+        T.n = (int)n;
+        T.G = L.G;
+        T.nstrips = L.nstrips;
+        T.bnd = A.bnd;
+        T.bnd_stride = A.bnd_stride;
+        T.key_gap = 4 * sc.gap;
+        T.seg = base + L.off_seg;
+        T.rw = base + L.off_rw;
+        T.seg_stride = L.seg_stride;
+        T.info = (int32_t*)(base + L.off_info);
+        T.info_stride = L.info_stride;
+        T.fix = (int32_t*)(base + L.off_fix);
+        T.summary = (int32_t*)(base + 128);
+        T.err = A.err;
+        T.path = path;
+        T.path_len = path_len;
+        T.score = score;
+        T.cap = m + n;
+        const unsigned blocks = (unsigned)((L.nstrips + kCoopWaves - 1) / kCoopWaves);
+        {
+            ProfScope ps("nw_tb_spec", st);
+            hipLaunchKernelGGL(k_tb_spec<kCoopC>, dim3(blocks), dim3(kCoopThreads), 0, st, T);
+        }
+        {
+            ProfScope ps("nw_tb_fix", st);
+            hipLaunchKernelGGL(k_tb_fix<kCoopC>, dim3(1), dim3(kWave), 0, st, T);
+        }
+        {
+            ProfScope ps("nw_tb_emit", st);
+            hipLaunchKernelGGL(k_tb_emit<kCoopC>, dim3(blocks), dim3(kCoopThreads), 0, st, T);
+        }
     }
     return hipGetLastError() == hipSuccess ? NW_OK : NW_EDEVICE;
 }

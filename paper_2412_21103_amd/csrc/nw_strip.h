@@ -103,10 +103,16 @@ struct TaggedIO {
     int32_t vinit;
     uint32_t epoch;
     int32_t* err;
+    bool in_local;   // the left neighbour runs on the same CU (same block)
+    bool out_local;  // the right neighbour runs on the same CU
     using Slot = uint64_t;
+    // Waves of one block share the CU's L1, so block-local neighbours use
+    // workgroup-scope accesses (plain, L1-coherent); other neighbours may sit
+    // on another XCD and use device-scope (sc1) accesses.
     __device__ __forceinline__ Slot load(int r, bool want) const {
         if (!(want && bin && r <= m)) return 0;
-        return __hip_atomic_load(bin + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return in_local ? __hip_atomic_load(bin + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                        : __hip_atomic_load(bin + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ __forceinline__ int32_t value(Slot x, int r) const {
         return r > m ? 0 : (bin ? (int32_t)(uint32_t)x : vinit);
@@ -115,9 +121,10 @@ struct TaggedIO {
         return !(want && bin && r <= m) || (uint32_t)(x >> 32) == epoch;
     }
     __device__ __forceinline__ void store(int r, int32_t v, bool want) const {
-        if (bout && want)
-            __hip_atomic_store(bout + r, ((uint64_t)epoch << 32) | (uint32_t)v, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        if (!(bout && want)) return;
+        const uint64_t x = ((uint64_t)epoch << 32) | (uint32_t)v;
+        if (out_local) __hip_atomic_store(bout + r, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else __hip_atomic_store(bout + r, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ __forceinline__ void fail() const {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -152,6 +159,7 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
                                                int kdx, int32_t vinit, const IO& io,
                                                uint32_t* __restrict__ dirs, uint32_t* lds, int ksel) {
     const int lane = lane_id();
+    const bool lane0 = (lane == 0);
     int32_t V[C];
     uint32_t acc[C];
     uint32_t bcode[C];
@@ -164,6 +172,9 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
     }
     int32_t Dg = vinit;
     int32_t R = io.value(wait_slot(io, lane + 1, lane < 16), lane + 1);
+    // boundary values for the refill of lanes 0..15 at the end of group 0
+    int rin = 16 + 1 + lane;
+    typename IO::Slot Rin = io.load(rin, lane < 16);
 
     const int NG = groups_for_rows(m);
     // window 0 covers groups [0, 8): rows [-63, 129)
@@ -206,9 +217,6 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
 #pragma unroll
         for (int k = 0; k < C; ++k) addr[k] = (base + bcode[k]) & 0x7FFFu;
 
-        // boundary values for the refill of lanes 0..15 at the end of this group
-        const int rin = 16 * (g + 1) + 1 + lane;
-        typename IO::Slot Rin = io.load(rin, lane < 16);
 
         // Narrow strips have too little work per step to hide the LDS latency
         // behind other waves, so their whole group of table reads is issued up
@@ -224,7 +232,7 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
 
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int32_t Lr = dpp_from_left(R, V[C - 1]);
+            const int32_t Lr = shift_in_from_left(R, V[C - 1], lane0);
             int32_t left = Lr;
             int32_t diag = Dg;
             int32_t tail = 0;  // the last column's previous value (+1 in the V domain)
@@ -256,6 +264,17 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
             R = dpp_from_right(tail, R);
             Dg = Lr;
         }
+        __builtin_amdgcn_sched_barrier(0);  // keep the refill's wait after the steps
+        // Group end.  Take this group's refill, then issue the next group's
+        // boundary load before this group's stores: vector-memory operations
+        // retire in order, so a load queued behind a device-coherent store
+        // would make the next refill wait for that store's round trip.
+        if (__builtin_amdgcn_ballot_w64(!io.ready(Rin, rin, lane < 16)) != 0)
+            Rin = wait_slot(io, rin, lane < 16);
+        const int32_t refill = io.value(Rin, rin);
+        rin += 16;
+        Rin = io.load(rin, lane < 16);
+        __builtin_amdgcn_sched_barrier(0);
         if constexpr (DIRS) {
             uint32_t* dst = dirs + ((size_t)g * kWave + lane) * C;
 #pragma unroll
@@ -264,10 +283,8 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
         {
             const int r = 16 * g + lane - 111;
             io.store(r, DIRS ? R - 1 : R, lane >= 48 && r >= 1 && r <= m);
-            if (__builtin_amdgcn_ballot_w64(!io.ready(Rin, rin, lane < 16)) != 0)
-                Rin = wait_slot(io, rin, lane < 16);
-            R = (lane < 16) ? io.value(Rin, rin) : R;
         }
+        R = (lane < 16) ? refill : R;
     }
     int32_t out = V[0];
 #pragma unroll
@@ -276,19 +293,23 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
     return out;
 }
 
-// Walk the stored directions of one pair from (m, n) back to (0, 0), one wave,
-// through a small LDS window of 4 groups x 16 lanes x C words anchored at the
-// current cell.  rev[q] gets the q-th move counted from the end.  Returns the
-// number of moves, or -1 if a stored tag is invalid.
+// Cached access to the stored direction words of one pair: a window of
+// 4 groups x 16 lanes x C words in LDS, anchored at the top-right (latest
+// group, highest lane) of the last miss, which suits walks that move to
+// lower steps and lower lanes.  Every lane of the wave calls tag() with the
+// same cell and gets the same (wave-uniform) answer.
 template <int C>
-__device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, int m, int n, int groups_per_strip,
-                             uint32_t* lds, uint8_t* __restrict__ rev) {
-    const int lane = lane_id();
-    int i = m, j = n;
-    int64_t q = 0;
-    int sw = -1, gw = 0, lw = 0;
-    constexpr int kCols = kWave * C;
-    while (i > 0 && j > 0) {
+struct DirWindow {
+    const uint32_t* dirs;
+    int G;
+    uint32_t* lds;  // >= 64*C words
+    int sw, gw, lw;
+    __device__ __forceinline__ DirWindow(const uint32_t* d, int groups, uint32_t* l)
+        : dirs(d), G(groups), lds(l), sw(-1), gw(0), lw(0) {}
+    // 2-bit tag of interior cell (i, j), 1 <= i, 1 <= j (3 diagonal, 2 vertical,
+    // 1 horizontal; 0 means corrupt data)
+    __device__ __forceinline__ int tag(int i, int j) {
+        constexpr int kCols = kWave * C;
         const int col0 = j - 1;
         const int s = col0 / kCols;
         const int w = col0 - s * kCols;
@@ -300,10 +321,11 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
             sw = s;
             gw = g;
             lw = l;
+            const int lane = lane_id();
             const int gq = gw - 3 + (lane >> 4);
             const int lq = lw - 15 + (lane & 15);
             if (gq >= 0 && lq >= 0) {
-                const uint32_t* src = dirs + (((size_t)sw * groups_per_strip + gq) * kWave + lq) * C;
+                const uint32_t* src = dirs + (((size_t)sw * G + gq) * kWave + lq) * C;
 #pragma unroll
                 for (int kk = 0; kk < C; ++kk) lds[lane * C + kk] = src[kk];
             }
@@ -311,7 +333,23 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
         }
         const int slot = ((g - gw + 3) << 4) + (l - lw + 15);
         const uint32_t word = (uint32_t)uniform((int32_t)lds[slot * C + k]);
-        const int tag = (int)((word >> (2 * (t & 15))) & 3u);
+        return (int)((word >> (2 * (t & 15))) & 3u);
+    }
+};
+
+// Walk the stored directions of one pair from (m, n) back to (0, 0), one wave,
+// through a small LDS window of 4 groups x 16 lanes x C words anchored at the
+// current cell.  rev[q] gets the q-th move counted from the end.  Returns the
+// number of moves, or -1 if a stored tag is invalid.
+template <int C>
+__device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, int m, int n, int groups_per_strip,
+                             uint32_t* lds, uint8_t* __restrict__ rev) {
+    const int lane = lane_id();
+    int i = m, j = n;
+    int64_t q = 0;
+    DirWindow<C> win(dirs, groups_per_strip, lds);
+    while (i > 0 && j > 0) {
+        const int tag = win.tag(i, j);
         if (tag == 0) return -1;
         const int mv = 4 - tag;
         rev[q] = (uint8_t)mv;  // every lane stores the same byte
