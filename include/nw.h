@@ -115,6 +115,38 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
                    size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Certified band (the paper's future-work aim of never missing an optimal
+ * alignment, Sec. 5, made exact).  Same inputs and outputs as
+ * nw_align_batch, and bit-identical results, but each pair first fills only
+ * the staircase of strips that covers
+ *     band(w) = { (i,j) : min(0,D) - w <= j - i <= max(0,D) + w },  D = n - m,
+ * with every cell outside it taken as -infinity.  The region's score S_R is
+ * certified when it beats the best score any path leaving band(w) can reach:
+ *     S_R > U_out(w) = c_d*(min(m,n) - w - 1) + gap*(|D| + 2w + 2),
+ *     c_d = max(match, mismatch)   (valid when 2*gap < c_d),
+ * which forces every optimal path inside the band, so score and tie-break
+ * path equal the full grid's.  Otherwise w doubles (0 becomes 1).  The full
+ * grid is used directly once w >= min(m,n), once the band's height reaches
+ * fallback_frac of m, or when 2*gap >= c_d.
+ *
+ * w_init (device int32[npairs], may be NULL: then w_default for all) gives
+ * each pair's first half-width, e.g. the band model's prediction.  Optional
+ * device outputs (NULL to skip): w_used[k] = final half-width (-1 = full
+ * grid); status[k] = bit 0 certified on the first pass, bits 1..5 number of
+ * doublings, bit 6 full grid, bit 7 certificate not applicable; cells[k] =
+ * cells swept over all passes.
+ * ------------------------------------------------------------------------ */
+int nw_align_batch_banded_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags,
+                                         size_t *bytes);
+
+int nw_align_batch_banded(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
+                          const int32_t *a_len, const int64_t *b_off, const int32_t *b_len,
+                          int32_t max_len, nw_scoring sc, uint32_t flags, const int32_t *w_init,
+                          int32_t w_default, float fallback_frac, int32_t *scores, uint8_t *paths,
+                          const int64_t *path_off, int32_t *path_len, int32_t *w_used,
+                          uint8_t *status, int64_t *cells, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * All-pairs score matrix for the centre-star multiple alignment front end
  * (paper Sec. 3.2, Eq. 2): out[i*nseq + j] (device int32, nseq x nseq,
  * row-major) = score of sequence i (rows) against sequence j (columns) for

@@ -18,7 +18,7 @@ __all__ = [
     "Scoring", "NWError", "PAPER_SCORING", "lib", "align", "align_batch", "allpairs",
     "align_workspace_size", "batch_workspace_size", "allpairs_workspace_size",
     "declared_functions", "MOVE_D", "MOVE_U", "MOVE_L", "SCORE_ONLY", "profile_begin",
-    "profile_end",
+    "profile_end", "align_batch_banded", "banded_workspace_size",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,6 +68,10 @@ def lib():
         L.nw_align_batch_workspace_size.argtypes = [_i32, _i32, _u32, ctypes.POINTER(_sz)]
         L.nw_align_batch.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _u32, _vp, _vp,
                                      _vp, _vp, _vp, _sz, _vp]
+        L.nw_align_batch_banded_workspace_size.argtypes = [_i32, _i32, _u32, ctypes.POINTER(_sz)]
+        L.nw_align_batch_banded.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _u32, _vp,
+                                            _i32, ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                            _vp, _sz, _vp]
         L.nw_allpairs_workspace_size.argtypes = [_i32, _i32, ctypes.POINTER(_sz)]
         L.nw_allpairs_scores.argtypes = [_i32, _vp, _vp, _vp, _i32, Scoring, _vp, _vp, _sz, _vp]
         L.nw_release_caches.restype = None
@@ -180,6 +184,49 @@ def align_batch(pool: torch.Tensor, a_off: torch.Tensor, a_len: torch.Tensor, b_
                               _ptr(path_off), _ptr(plen), _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "nw_align_batch")
     return scores, paths, path_off, plen
+
+
+def banded_workspace_size(npairs: int, max_len: int, flags: int = 0) -> int:
+    out = _sz(0)
+    _check(lib().nw_align_batch_banded_workspace_size(int(npairs), int(max_len), int(flags),
+                                                      ctypes.byref(out)),
+           "nw_align_batch_banded_workspace_size")
+    return int(out.value)
+
+
+def align_batch_banded(pool: torch.Tensor, a_off: torch.Tensor, a_len: torch.Tensor,
+                       b_off: torch.Tensor, b_len: torch.Tensor, max_len: int,
+                       scoring=PAPER_SCORING, w_init: torch.Tensor | None = None, w_default: int = 0,
+                       fallback_frac: float = 0.5, score_only: bool = False,
+                       path_off: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                       stream=None):
+    """Certified-band batch.  Returns ``(scores, paths, path_off, path_len, w_used, status,
+    cells)`` (paths/path_off/path_len are None with ``score_only``)."""
+    npairs = int(a_len.numel())
+    flags = SCORE_ONLY if score_only else 0
+    dev = _dev()
+    ws = _workspace(banded_workspace_size(npairs, max_len, flags), workspace)
+    scores = torch.empty(npairs, dtype=torch.int32, device=dev)
+    w_used = torch.empty(npairs, dtype=torch.int32, device=dev)
+    status = torch.empty(npairs, dtype=torch.uint8, device=dev)
+    cells = torch.empty(npairs, dtype=torch.int64, device=dev)
+    paths = plen = None
+    if not score_only:
+        caps = a_len.to(torch.int64) + b_len.to(torch.int64)
+        if path_off is None:
+            path_off = torch.zeros(npairs, dtype=torch.int64, device=dev)
+            if npairs > 1:
+                path_off[1:] = torch.cumsum(caps, 0)[:-1]
+        total = int((path_off[-1] + caps[-1]).item()) if npairs else 1
+        paths = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+        plen = torch.empty(npairs, dtype=torch.int32, device=dev)
+    st = lib().nw_align_batch_banded(npairs, _ptr(pool), _ptr(a_off), _ptr(a_len), _ptr(b_off),
+                                     _ptr(b_len), int(max_len), _sc(scoring), flags, _ptr(w_init),
+                                     int(w_default), float(fallback_frac), _ptr(scores), _ptr(paths),
+                                     _ptr(path_off), _ptr(plen), _ptr(w_used), _ptr(status),
+                                     _ptr(cells), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "nw_align_batch_banded")
+    return scores, paths, path_off, plen, w_used, status, cells
 
 
 def allpairs(pool: torch.Tensor, off: torch.Tensor, lens: torch.Tensor, max_len: int,

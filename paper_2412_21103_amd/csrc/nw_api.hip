@@ -272,6 +272,60 @@ int nw_align_batch(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
     return launch_batch(J, ws, ws_bytes, (hipStream_t)stream, di);
 }
 
+// ---------------------------------------------------------- certified band
+
+int nw_align_batch_banded_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags,
+                                         size_t* bytes) {
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    *bytes = batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di, true);
+    return NW_OK;
+}
+
+int nw_align_batch_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
+                          const int32_t* a_len, const int64_t* b_off, const int32_t* b_len,
+                          int32_t max_len, nw_scoring sc, uint32_t flags, const int32_t* w_init,
+                          int32_t w_default, float fallback_frac, int32_t* scores, uint8_t* paths,
+                          const int64_t* path_off, int32_t* path_len, int32_t* w_used,
+                          uint8_t* status, int64_t* cells, void* ws, size_t ws_bytes, void* stream) {
+    if (npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY) || w_default < 0) return NW_EINVAL;
+    if (!(fallback_frac > 0.f) || fallback_frac > 64.f) return NW_EINVAL;
+    const bool dirs = !(flags & NW_SCORE_ONLY);
+    int st = check_lengths(max_len, max_len, sc);
+    if (st) return st;
+    if ((st = check_scoring(sc, dirs))) return st;
+    if (npairs == 0) return NW_OK;
+    if (!pool || !a_off || !a_len || !b_off || !b_len || !scores || !ws) return NW_EINVAL;
+    if (dirs && (!paths || !path_off || !path_len)) return NW_EINVAL;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    BatchJob J{};
+    J.allpairs = false;
+    J.njobs = npairs;
+    J.pool = pool;
+    J.a_off = a_off;
+    J.a_len = a_len;
+    J.b_off = b_off;
+    J.b_len = b_len;
+    J.max_len = std::max(max_len, 1);
+    J.sc = sc;
+    J.dirs = dirs;
+    J.scores = scores;
+    J.paths = paths;
+    J.path_off = path_off;
+    J.path_len = dirs ? path_len : nullptr;
+    J.banded = true;
+    J.w_init = w_init;
+    J.w_default = w_default;
+    J.frac_1024 = (int32_t)(fallback_frac * 1024.f);
+    J.w_used = w_used;
+    J.status = status;
+    J.cells = cells;
+    return launch_batch(J, ws, ws_bytes, (hipStream_t)stream, di);
+}
+
 // -------------------------------------------------------------- all pairs
 
 int nw_allpairs_workspace_size(int32_t nseq, int32_t max_len, size_t* bytes) {

@@ -21,6 +21,15 @@ constexpr int kBuckets = 64;
 
 struct KArgs {
     int32_t njobs, nseq;
+    // certified band (nw_align_batch_banded)
+    const int32_t* w_init;  // per pair initial half-width, or null
+    int32_t w_default;
+    int32_t frac_1024;      // fall back to the full grid once the band is this fraction of m (x1024)
+    int32_t cd;             // max(match, mismatch)
+    int32_t band_ok;        // the certificate applies (2 gap < cd)
+    int32_t* w_used;
+    uint8_t* status;
+    int64_t* cells;
     const uint8_t* pool;
     const int64_t* a_off;
     const int32_t* a_len;
@@ -137,7 +146,58 @@ __device__ __forceinline__ void fence_wave_memory() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-template <int C, bool DIRS, bool ALLPAIRS>
+constexpr int32_t kNegV = -(1 << 30) + 1;  // -infinity in the V domain (ends in tag 1)
+constexpr int32_t kNegW = -(1 << 29);      // -infinity in the W domain
+
+// Fill one pair over the region {rows r0(s)+1 .. re(s)} of every strip s:
+// the whole grid when `full`, else the staircase of strips that covers
+// band(w) = { min(0,D) - w <= j - i <= max(0,D) + w }, D = n - m.  Cells
+// outside the region are -infinity; the first row and column keep their
+// values.  Returns V (or W) at (m, n); *G_out gets the direction groups per
+// strip and *cells the number of cells swept.
+template <int C, bool DIRS>
+__device__ __forceinline__ int32_t fill_pair(const KArgs& A, const uint8_t* pa, const uint8_t* pb,
+                                             int m, int n, bool full, int w, int32_t* bnd,
+                                             uint32_t* dirs, uint32_t* lds, int* G_out,
+                                             int64_t* cells) {
+    constexpr int kCols = kWave * C;
+    const int32_t vinit = DIRS ? 1 : 0;
+    const int32_t vneg = DIRS ? kNegV : kNegW;
+    const int lo_d = min(0, n - m), hi_d = max(0, n - m);
+    const int nstrips = (n + kCols - 1) / kCols;
+    const int height = full ? m : min(m, kCols + hi_d - lo_d + 2 * w);
+    const int G = groups_for_rows(height);
+    *G_out = G;
+    int32_t vlast = 0;
+    int prev_lo = 1, prev_hi = m;  // previous strip's rows
+    int64_t swept = 0;
+    for (int s = 0; s < nstrips; ++s) {
+        const int j0 = s * kCols;
+        const int rs = full ? 1 : max(1, j0 + 1 - hi_d - w);
+        const int re = full ? m : min(m, j0 + kCols - lo_d + w);
+        const int r0 = rs - 1, rows = re - rs + 1;
+        const int ksel = (n - 1 - j0) % C;
+        PlainIO io{s == 0 ? nullptr : bnd, s == nstrips - 1 ? nullptr : bnd, rows, vinit};
+        io.r0 = r0;
+        io.in_hi = (s == 0) ? m : prev_hi;
+        io.beyond = full ? 0 : vneg;
+        const int32_t vtop = (r0 == 0) ? vinit : vneg;
+        int32_t dg0 = vinit;
+        if (s > 0 && r0 > 0) dg0 = (r0 >= prev_lo && r0 <= prev_hi) ? bnd[r0] : vneg;
+        vlast = sweep_strip<C, DIRS>(pa + r0, rows, pb, n, j0, A.kdm, A.kdx, vtop, dg0, io,
+                                     DIRS ? dirs + (size_t)s * G * kWave * C : nullptr, lds, ksel);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        prev_lo = rs;
+        prev_hi = re;
+        swept += (int64_t)rows * min(kCols, n - j0);
+    }
+    *cells += swept;
+    const int lsel = (n - 1 - (nstrips - 1) * kCols) / C;
+    return __builtin_amdgcn_readlane(vlast, lsel);
+}
+
+template <int C, bool DIRS, bool ALLPAIRS, bool BANDED>
 __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
     __shared__ uint32_t smem[kWavesPerBlock][StripShape<C>::kLdsWords];
     const int wave = threadIdx.x >> 6;
@@ -147,7 +207,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
     int32_t* bnd = A.bnd + slot * A.bnd_stride;
     uint32_t* dirs = DIRS ? A.dirs + slot * A.dirs_stride : nullptr;
     uint8_t* rev = DIRS ? A.rev + slot * A.rev_stride : nullptr;
-    const int32_t vinit = DIRS ? 1 : 0;
     constexpr int kCols = kWave * C;
 
     // The job loop keeps every lane active on every path: the queue ticket
@@ -177,24 +236,43 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
                 plen = m + n;
             }
         } else {
-            const int nstrips = (n + kCols - 1) / kCols;
-            const int G = groups_for_rows(m);
-            int32_t vlast = 0;
-            for (int s = 0; s < nstrips; ++s) {
-                const int j0 = s * kCols;
-                const int ksel = (n - 1 - j0) % C;
-                const PlainIO io{s == 0 ? nullptr : bnd, s == nstrips - 1 ? nullptr : bnd, m, vinit};
-                vlast = sweep_strip<C, DIRS>(P.a, m, P.b, n, j0, A.kdm, A.kdx, vinit, io,
-                                             DIRS ? dirs + (size_t)s * G * kWave * C : nullptr,
-                                             lds, ksel);
-                fence_wave_memory();
+            int G = 0;
+            int64_t cells = 0;
+            bool full = true;
+            int w = 0;
+            int passes = 0;
+            if constexpr (BANDED) {
+                // certified band: double w until the region score beats the best
+                // score any path leaving band(w) can reach, or the band is so
+                // wide that the full grid is cheaper
+                w = max(0, A.w_init ? A.w_init[job] : A.w_default);
+                const int mn = min(m, n);
+                const int64_t dlt = n > m ? n - m : m - n;
+                for (;;) {
+                    full = !A.band_ok || w >= mn ||
+                           (int64_t)(kCols + dlt + 2 * (int64_t)w) * 1024 >= (int64_t)A.frac_1024 * m;
+                    const int32_t v = fill_pair<C, DIRS>(A, P.a, P.b, m, n, full, w, bnd, dirs, lds, &G, &cells);
+                    ++passes;
+                    score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
+                    if (full) break;
+                    const int64_t u_out = (int64_t)A.cd * (mn - w - 1) + (int64_t)A.gap * (dlt + 2 * (int64_t)w + 2);
+                    if ((int64_t)score > u_out) break;
+                    w = max(1, 2 * w);
+                }
+                if (A.w_used) A.w_used[job] = full ? -1 : w;
+                if (A.status) {
+                    const int doublings = min(passes - 1, 31);
+                    A.status[job] = (uint8_t)((passes == 1 && !full ? 1 : 0) | (doublings << 1) |
+                                              (full ? 0x40 : 0) | (A.band_ok ? 0 : 0x80));
+                }
+                if (A.cells) A.cells[job] = cells;
+            } else {
+                const int32_t v = fill_pair<C, DIRS>(A, P.a, P.b, m, n, true, 0, bnd, dirs, lds, &G, &cells);
+                score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
             }
-            const int lastj0 = (nstrips - 1) * kCols;
-            const int lsel = (n - 1 - lastj0) / C;
-            const int32_t v = __builtin_amdgcn_readlane(vlast, lsel);
-            score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
             if constexpr (DIRS && !ALLPAIRS) {
-                int64_t len = walk_back<C>(dirs, m, n, G, lds, rev);
+                const int band_hi = full ? (1 << 30) : max(0, n - m) + w;
+                int64_t len = walk_back<C>(dirs, m, n, G, lds, rev, band_hi);
                 fence_wave_memory();
                 if (len < 0) {
                     plen = -2;
@@ -231,12 +309,22 @@ struct Layout {
     int64_t bnd_stride, dirs_stride, rev_stride;
 };
 
-static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di) {
+// Per-call workspace for direction slots is capped: a persistent wave needs a
+// slot that holds the full grid of the largest pair, so very long pairs get
+// fewer waves.
+constexpr size_t kSlotBudget = size_t(48) << 30;
+
+static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di, bool banded = false) {
     Layout L{};
-    L.C = choose_cols(max_len);
+    L.C = banded ? 2 : choose_cols(max_len);
     const int64_t cols = (int64_t)kWave * L.C;
     const int64_t want = ((int64_t)njobs + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t cap = (int64_t)di.cus * kBlocksPerCu;
+    int64_t cap = (int64_t)di.cus * kBlocksPerCu;
+    if (dirs) {
+        const int64_t ml = std::max<int32_t>(max_len, 1);
+        const int64_t slot = ((ml + cols - 1) / cols) * groups_for_rows((int)ml) * kWave * L.C * 4;
+        cap = std::max<int64_t>(1, std::min<int64_t>(cap, (int64_t)(kSlotBudget / (size_t)slot / kWavesPerBlock)));
+    }
     L.grid = std::max<int64_t>(1, std::min(want, cap));
     L.nslots = L.grid * kWavesPerBlock;
     const int64_t ml = std::max<int32_t>(max_len, 1);
@@ -258,31 +346,34 @@ static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const Device
     return L;
 }
 
-size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di) {
-    return layout_for(njobs, max_len, dirs, di).total;
+size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di, bool banded) {
+    return layout_for(njobs, max_len, dirs, di, banded).total;
 }
 
-template <int C, bool DIRS, bool ALLPAIRS>
+template <int C, bool DIRS, bool ALLPAIRS, bool BANDED>
 static void launch_engine(const KArgs& A, int64_t grid, hipStream_t st) {
-    ProfScope ps(ALLPAIRS ? "nw_allpairs" : (DIRS ? "nw_batch" : "nw_batch_score"), st);
-    hipLaunchKernelGGL((k_batch<C, DIRS, ALLPAIRS>), dim3((unsigned)grid), dim3(kBlockThreads), 0, st, A);
+    ProfScope ps(BANDED ? (DIRS ? "nw_batch_banded" : "nw_batch_banded_score")
+                        : (ALLPAIRS ? "nw_allpairs" : (DIRS ? "nw_batch" : "nw_batch_score")),
+                 st);
+    hipLaunchKernelGGL((k_batch<C, DIRS, ALLPAIRS, BANDED>), dim3((unsigned)grid), dim3(kBlockThreads), 0,
+                       st, A);
 }
 
-template <bool ALLPAIRS>
+template <bool ALLPAIRS, bool BANDED>
 static void launch_c(int C, bool dirs, const KArgs& A, int64_t grid, hipStream_t st) {
     if (dirs) {
-        if (C == 8) launch_engine<8, true, ALLPAIRS>(A, grid, st);
-        else if (C == 4) launch_engine<4, true, ALLPAIRS>(A, grid, st);
-        else launch_engine<2, true, ALLPAIRS>(A, grid, st);
+        if (C == 8) launch_engine<8, true, ALLPAIRS, BANDED>(A, grid, st);
+        else if (C == 4) launch_engine<4, true, ALLPAIRS, BANDED>(A, grid, st);
+        else launch_engine<2, true, ALLPAIRS, BANDED>(A, grid, st);
     } else {
-        if (C == 8) launch_engine<8, false, ALLPAIRS>(A, grid, st);
-        else if (C == 4) launch_engine<4, false, ALLPAIRS>(A, grid, st);
-        else launch_engine<2, false, ALLPAIRS>(A, grid, st);
+        if (C == 8) launch_engine<8, false, ALLPAIRS, BANDED>(A, grid, st);
+        else if (C == 4) launch_engine<4, false, ALLPAIRS, BANDED>(A, grid, st);
+        else launch_engine<2, false, ALLPAIRS, BANDED>(A, grid, st);
     }
 }
 
 int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st, const DeviceInfo& di) {
-    const Layout L = layout_for(job.njobs, job.max_len, job.dirs, di);
+    const Layout L = layout_for(job.njobs, job.max_len, job.dirs, di, job.banded);
     if (ws_bytes < L.total) return NW_ENOSPC;
     if (job.njobs == 0) return NW_OK;
     uint8_t* base = (uint8_t*)ws;
@@ -305,6 +396,14 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.path_len = job.path_len;
     A.path_len64 = job.path_len64;
     A.matrix = job.matrix;
+    A.w_init = job.w_init;
+    A.w_default = job.w_default;
+    A.frac_1024 = job.frac_1024;
+    A.cd = std::max(job.sc.match, job.sc.mismatch);
+    A.band_ok = 2 * job.sc.gap < A.cd ? 1 : 0;
+    A.w_used = job.w_used;
+    A.status = job.status;
+    A.cells = job.cells;
     A.queue = (int32_t*)base;
     A.hist = (int32_t*)(base + 64 * 4);
     A.cursor = (int32_t*)(base + 128 * 4);
@@ -322,12 +421,13 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
         hipLaunchKernelGGL(k_hist<true>, dim3(pb), dim3(256), 0, st, A);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor);
         hipLaunchKernelGGL(k_scatter<true>, dim3(pb), dim3(256), 0, st, A);
-        launch_c<true>(L.C, job.dirs, A, L.grid, st);
+        launch_c<true, false>(L.C, job.dirs, A, L.grid, st);
     } else {
         hipLaunchKernelGGL(k_hist<false>, dim3(pb), dim3(256), 0, st, A);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor);
         hipLaunchKernelGGL(k_scatter<false>, dim3(pb), dim3(256), 0, st, A);
-        launch_c<false>(L.C, job.dirs, A, L.grid, st);
+        if (job.banded) launch_c<false, true>(L.C, job.dirs, A, L.grid, st);
+        else launch_c<false, false>(L.C, job.dirs, A, L.grid, st);
     }
     return hipGetLastError() == hipSuccess ? NW_OK : NW_EDEVICE;
 }

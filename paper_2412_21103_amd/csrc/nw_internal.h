@@ -59,6 +59,14 @@ struct BatchJob {
     int32_t* path_len;
     int64_t* path_len64; // single-pair calls report an int64 length
     int32_t* matrix;     // all-pairs mode
+    // certified band
+    bool banded;
+    const int32_t* w_init;
+    int32_t w_default;
+    int32_t frac_1024;
+    int32_t* w_used;
+    uint8_t* status;
+    int64_t* cells;
 };
 
 // Cooperative single-pair engine (nw_single.hip): used for one pair with at
@@ -69,7 +77,8 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
                 bool dirs, int32_t* score, uint8_t* path, int64_t* path_len, void* ws,
                 size_t ws_bytes, hipStream_t stream, const DeviceInfo& di);
 
-size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di);
+size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di,
+                             bool banded = false);
 int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t stream,
                  const DeviceInfo& di);
 

@@ -79,7 +79,8 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
                               A.err,
                               wave > 0,
                               wave < kCoopWaves - 1};
-            const int32_t v = sweep_strip<C, DIRS>(A.a, A.m, A.b, A.n, j0, A.kdm, A.kdx, A.vinit, io,
+            const int32_t v = sweep_strip<C, DIRS>(A.a, A.m, A.b, A.n, j0, A.kdm, A.kdx, A.vinit,
+                                                   A.vinit, io,
                                                    DIRS ? A.dirs + (size_t)s * A.G * kWave * C : nullptr,
                                                    lds, ksel);
             if (s == A.nstrips - 1) {

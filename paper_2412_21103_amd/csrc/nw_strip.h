@@ -67,25 +67,33 @@ __device__ __forceinline__ void write_window(uint32_t* win, const uint8_t* a, in
 }
 
 // Boundary IO for a wave that owns every strip of its pair: the previous
-// strip's right column sits in the wave's own scratch (bin), the next strip's
-// goes to the same buffer (bout; reads of a row happen before its overwrite).
-// Rows beyond m read 0, which never wins; a missing bin means the grid's
-// first column (vinit).
+// strip's right column sits in the wave's own scratch (bin, indexed by grid
+// row), the next strip's goes to the same buffer (bout; reads of a row happen
+// before its overwrite).  The sweep may cover only grid rows r0+1 .. r0+m
+// (a band); its rows are numbered locally from 1.  Inputs for grid rows above
+// in_hi, or beyond the sweep, lie outside the previous strip's region and
+// read `beyond`, a value that never wins (0, or the -infinity sentinel of a
+// band).  A missing bin means the grid's first column (vinit).
 struct PlainIO {
     const int32_t* bin;
     int32_t* bout;
     int m;
     int32_t vinit;
+    int r0 = 0;
+    int in_hi = 1 << 30;
+    int32_t beyond = 0;
     using Slot = int32_t;
     __device__ __forceinline__ Slot load(int r, bool want) const {
-        return (want && bin && r <= m) ? bin[r] : 0;
+        return (want && bin && r <= m && r0 + r <= in_hi) ? bin[r0 + r] : 0;
     }
     __device__ __forceinline__ int32_t value(Slot x, int r) const {
-        return r > m ? 0 : (bin ? x : vinit);
+        if (r > m) return beyond;
+        if (!bin) return vinit;
+        return (r0 + r <= in_hi) ? x : beyond;
     }
     __device__ __forceinline__ bool ready(Slot, int, bool) const { return true; }
     __device__ __forceinline__ void store(int r, int32_t v, bool want) const {
-        if (bout && want) bout[r] = v;
+        if (bout && want) bout[r0 + r] = v;
     }
     __device__ __forceinline__ void fail() const {}
     __device__ __forceinline__ bool failed() const { return false; }
@@ -153,10 +161,15 @@ __device__ __forceinline__ typename IO::Slot wait_slot(const IO& io, int r, bool
 
 // Sweep one strip.  Returns, per lane, V (or W) of its column `ksel` after
 // the last row (the frozen final value).
+// `a` points at the sweep's first row and `m` counts its rows (a band sweeps
+// grid rows r0+1 .. r0+m with a = seq + r0).  Every lane starts from `vtop`,
+// the row above the sweep (the grid's first row, or -infinity inside a band),
+// except that lane 0's first diagonal input is `dg0`, the previous strip's
+// last column one row above the sweep.
 template <int C, bool DIRS, class IO>
 __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, int m,
                                                const uint8_t* __restrict__ b, int n, int j0, int kdm,
-                                               int kdx, int32_t vinit, const IO& io,
+                                               int kdx, int32_t vtop, int32_t dg0, const IO& io,
                                                uint32_t* __restrict__ dirs, uint32_t* lds, int ksel) {
     const int lane = lane_id();
     const bool lane0 = (lane == 0);
@@ -165,12 +178,12 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
     uint32_t bcode[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        V[k] = vinit;
+        V[k] = vtop;
         acc[k] = 0;
         int j = j0 + C * lane + k;
         bcode[k] = (j < n) ? (uint32_t)(b[j] & 3) : 0u;
     }
-    int32_t Dg = vinit;
+    int32_t Dg = lane0 ? dg0 : vtop;
     int32_t R = io.value(wait_slot(io, lane + 1, lane < 16), lane + 1);
     // boundary values for the refill of lanes 0..15 at the end of group 0
     int rin = 16 + 1 + lane;
@@ -298,14 +311,18 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
 // group, highest lane) of the last miss, which suits walks that move to
 // lower steps and lower lanes.  Every lane of the wave calls tag() with the
 // same cell and gets the same (wave-uniform) answer.
+//
+// For a band, strip s swept grid rows r0(s)+1 .. with r0(s) =
+// max(0, s*64*C - band_hi) and every strip has G groups of storage.
 template <int C>
 struct DirWindow {
     const uint32_t* dirs;
     int G;
     uint32_t* lds;  // >= 64*C words
+    int band_hi;
     int sw, gw, lw;
-    __device__ __forceinline__ DirWindow(const uint32_t* d, int groups, uint32_t* l)
-        : dirs(d), G(groups), lds(l), sw(-1), gw(0), lw(0) {}
+    __device__ __forceinline__ DirWindow(const uint32_t* d, int groups, uint32_t* l, int bhi = 1 << 30)
+        : dirs(d), G(groups), lds(l), band_hi(bhi), sw(-1), gw(0), lw(0) {}
     // 2-bit tag of interior cell (i, j), 1 <= i, 1 <= j (3 diagonal, 2 vertical,
     // 1 horizontal; 0 means corrupt data)
     __device__ __forceinline__ int tag(int i, int j) {
@@ -315,7 +332,8 @@ struct DirWindow {
         const int w = col0 - s * kCols;
         const int l = w / C;
         const int k = w - l * C;
-        const int t = i - 1 + l;
+        const int r0 = max(0, s * kCols - band_hi);
+        const int t = i - r0 - 1 + l;
         const int g = t >> 4;
         if (s != sw || g > gw || g < gw - 3 || l > lw || l < lw - 15) {
             sw = s;
@@ -342,12 +360,13 @@ struct DirWindow {
 // current cell.  rev[q] gets the q-th move counted from the end.  Returns the
 // number of moves, or -1 if a stored tag is invalid.
 template <int C>
-__device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, int m, int n, int groups_per_strip,
-                             uint32_t* lds, uint8_t* __restrict__ rev) {
+__device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, int m, int n,
+                                             int groups_per_strip, uint32_t* lds,
+                                             uint8_t* __restrict__ rev, int band_hi = 1 << 30) {
     const int lane = lane_id();
     int i = m, j = n;
     int64_t q = 0;
-    DirWindow<C> win(dirs, groups_per_strip, lds);
+    DirWindow<C> win(dirs, groups_per_strip, lds, band_hi);
     while (i > 0 && j > 0) {
         const int tag = win.tag(i, j);
         if (tag == 0) return -1;

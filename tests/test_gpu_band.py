@@ -1,0 +1,120 @@
+"""Certified band: results bit-identical to the oracle (and to the full-grid
+batch) for every starting half-width, with doubling and fallback exercised."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import band
+from workloads import config_band_batch, pack_pairs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2412_21103_amd as nwp  # noqa: E402
+from gpu_util import say  # noqa: E402
+
+P = (1, -1, -1)
+
+
+def _dev(x, dt):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to("cuda")
+
+
+def run_band(pairs, w_init, scoring=P, w_default=0, frac=0.5):
+    pool, ao, al, bo, bl = pack_pairs(pairs)
+    ml = int(max(al.max(), bl.max()))
+    wi = None if w_init is None else _dev(w_init, np.int32)
+    s, paths, poff, plen, wu, st, cells = nwp.align_batch_banded(
+        _dev(pool, np.uint8), _dev(ao, np.int64), _dev(al, np.int32), _dev(bo, np.int64),
+        _dev(bl, np.int32), ml, scoring, w_init=wi, w_default=w_default, fallback_frac=frac)
+    torch.cuda.synchronize()
+    paths = paths.cpu().numpy()
+    poff = poff.cpu().numpy()
+    plen = plen.cpu().numpy()
+    out = [paths[poff[k]:poff[k] + plen[k]] for k in range(len(pairs))]
+    return s.cpu().numpy(), out, wu.cpu().numpy(), st.cpu().numpy(), cells.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def small_band_batch():
+    pairs = config_band_batch(seed=77, npairs=48, lo=300, hi=2500)
+    ref = [oracle.align(a, b, P) for a, b in zip(pairs.a, pairs.b)]
+    return pairs, ref
+
+
+def check_equal(pairs, ref, s, paths, tag):
+    for k in range(len(pairs)):
+        assert s[k] == ref[k][0], (tag, k, s[k], ref[k][0])
+        assert paths[k].tolist() == ref[k][1].tolist(), (tag, k)
+
+
+def test_band_with_certified_widths(small_band_batch):
+    pairs, ref = small_band_batch
+    wc = np.array([band.w_cert(r[0], len(a), len(b), P) for r, a, b in zip(ref, pairs.a, pairs.b)])
+    say("band: w_init = w_cert")
+    s, paths, wu, st, cells = run_band(pairs, wc)
+    check_equal(pairs, ref, s, paths, "w_cert")
+    # a start at w_cert certifies on the first pass unless the band is wide
+    # enough to fall back to the full grid
+    first = (st & 1) == 1
+    fullg = (st & 0x40) != 0
+    assert (first | fullg).all()
+    assert first.sum() >= len(pairs) // 2
+
+
+def test_band_doubling_from_zero(small_band_batch):
+    pairs, ref = small_band_batch
+    say("band: w_init = 0 (doubling)")
+    s, paths, wu, st, cells = run_band(pairs, None, w_default=0)
+    check_equal(pairs, ref, s, paths, "w0=0")
+    doublings = (st >> 1) & 31
+    assert doublings.max() >= 2
+    # the certified width is never below the closed-form minimum
+    for k in range(len(pairs)):
+        if wu[k] >= 0:
+            assert wu[k] >= band.w_cert(ref[k][0], len(pairs.a[k]), len(pairs.b[k]), P)
+
+
+def test_band_forced_fallback(small_band_batch):
+    pairs, ref = small_band_batch
+    say("band: fallback fraction tiny -> full grid")
+    s, paths, wu, st, cells = run_band(pairs, None, w_default=3, frac=1e-4)
+    check_equal(pairs, ref, s, paths, "fallback")
+    assert ((st & 0x40) != 0).all() and (wu == -1).all()
+    m = np.array([len(a) for a in pairs.a], np.int64)
+    n = np.array([len(b) for b in pairs.b], np.int64)
+    assert (cells >= m * n).all()
+
+
+def test_band_inapplicable_scoring():
+    # 2*gap >= max(match, mismatch): the certificate does not apply, so the
+    # band silently runs the full grid
+    sc = (1, -1, 1)
+    pairs = config_band_batch(seed=78, npairs=6, lo=200, hi=600)
+    ref = [oracle.align(a, b, sc) for a, b in zip(pairs.a, pairs.b)]
+    say("band: inapplicable scoring")
+    s, paths, wu, st, cells = run_band(pairs, None, scoring=sc, w_default=2)
+    check_equal(pairs, ref, s, paths, "inapplicable")
+    assert ((st & 0x80) != 0).all()
+
+
+def test_band_matches_full_batch(small_band_batch):
+    pairs, ref = small_band_batch
+    pool, ao, al, bo, bl = pack_pairs(pairs)
+    ml = int(max(al.max(), bl.max()))
+    say("band vs full batch, other scoring")
+    sc = (2, -3, -2)
+    s_full, paths_full, poff, plen = nwp.align_batch(
+        _dev(pool, np.uint8), _dev(ao, np.int64), _dev(al, np.int32), _dev(bo, np.int64),
+        _dev(bl, np.int32), ml, sc)
+    torch.cuda.synchronize()
+    s, paths, wu, st, cells = run_band(pairs, None, scoring=sc, w_default=8)
+    assert (s == s_full.cpu().numpy()).all()
+    pf = paths_full.cpu().numpy()
+    po = poff.cpu().numpy()
+    pl = plen.cpu().numpy()
+    for k in range(len(pairs)):
+        assert paths[k].tolist() == pf[po[k]:po[k] + pl[k]].tolist()
