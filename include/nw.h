@@ -134,7 +134,9 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  * device outputs (NULL to skip): w_used[k] = final half-width (-1 = full
  * grid); status[k] = bit 0 certified on the first pass, bits 1..5 number of
  * doublings, bit 6 full grid, bit 7 certificate not applicable; cells[k] =
- * cells swept over all passes.
+ * cells swept over all passes.  A pair with m == 0 or n == 0 reports
+ * w_used -1, the full-grid bit and 0 cells; a pair over max_len reports
+ * w_used -1, status 0 and 0 cells.
  * ------------------------------------------------------------------------ */
 int nw_align_batch_banded_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags,
                                          size_t *bytes);
@@ -162,6 +164,112 @@ int nw_allpairs_workspace_size(int32_t nseq, int32_t max_len, size_t *bytes);
 int nw_allpairs_scores(int32_t nseq, const uint8_t *pool, const int64_t *off,
                        const int32_t *len, int32_t max_len, nw_scoring sc, int32_t *out,
                        void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Band model: a learned first half-width for the certified band.
+ *
+ * The paper closes (Sec. 5) by naming efficiency without missing an optimal
+ * alignment as the aim of further work.  The certified band above never
+ * misses one; this small network only predicts, per pair, the half-width at
+ * which the certificate will first succeed, so that most pairs pass on the
+ * first banded sweep.  Its outputs change speed, never scores or paths.
+ *
+ * Features (NW_MLP_INPUTS = 259 per pair, float32):
+ *   x[0..2] = m/20000, n/20000, (m-n)/20000;
+ *   x[3+c]  = (count of 4-mer c in a - count in b) / max(m, n, 1), where the
+ *             4-mer with codes c0 c1 c2 c3 has index 64 c0 + 16 c1 + 4 c2 + c3.
+ * Network: 259 -> 64 ReLU -> 64 ReLU -> 1.  Parameters are one flat vector of
+ * NW_MLP_PARAMS floats in this order: W1[64][259] (row = hidden unit), b1[64],
+ * W2[64][64], b2[64], w3[64], b3.  The layers use the bfloat16 copy of W1, W2
+ * and w3 (round to nearest even) and the float32 biases; activations and
+ * sums are float32.
+ * Target: log1p(w_cert), w_cert = the smallest half-width the certificate
+ * of nw_align_batch_banded accepts for the pair's score S (capped at
+ * min(m,n)).  Loss: mean pinball loss with quantile tau over the batch
+ * (tau near 1 makes under-prediction, which costs a doubling, rare).
+ * Optimiser: Adam, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected.
+ * ------------------------------------------------------------------------ */
+#define NW_MLP_INPUTS 259
+#define NW_MLP_HIDDEN 64
+#define NW_MLP_PARAMS 20865
+
+/* Model state.  Every pointer is a device array of NW_MLP_PARAMS entries owned
+ * by the caller.  adam_m and adam_v (zero-initialised by the caller) are only
+ * read by the training calls and may be NULL otherwise.  step (host) counts
+ * the Adam updates taken; each training update increments it. */
+typedef struct nw_mlp {
+    float *params;         /* float32 master weights                     */
+    uint16_t *params_bf16; /* bfloat16 copy (bit patterns), same layout  */
+    float *adam_m;         /* Adam first moments                         */
+    float *adam_v;         /* Adam second moments                        */
+    int64_t step;
+} nw_mlp;
+
+/* Rewrite params_bf16 from params (after the caller sets or loads the master
+ * weights). */
+int nw_mlp_sync(const nw_mlp *mlp, void *stream);
+
+/* Features of npairs pairs (same pair description as nw_align_batch) into
+ * x[npairs][NW_MLP_INPUTS] (device). */
+int nw_mlp_features(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
+                    const int32_t *a_len, const int64_t *b_off, const int32_t *b_len, float *x,
+                    void *stream);
+
+/* yhat[r] (device float32) = network output for row x[r] (r < rows). */
+int nw_mlp_forward(const nw_mlp *mlp, int32_t rows, const float *x, float *yhat, void *stream);
+
+/* Half-widths from predictions of log1p(w): w[k] = ceil(expm1(max(yhat[k],0)) *
+ * (1 + margin)) clamped to [0, max(a_len[k], b_len[k])], evaluated in double.
+ * margin >= 0. */
+int nw_mlp_widths(int32_t npairs, const float *yhat, const int32_t *a_len, const int32_t *b_len,
+                  float margin, int32_t *w, void *stream);
+
+/* Training labels from full-grid scores (e.g. nw_align_batch with
+ * NW_SCORE_ONLY): w_cert[k] (device int32, may be NULL) and target[k] =
+ * log1pf(w_cert[k]) (device float32, may be NULL).  Needs a scoring for
+ * which the certificate applies (2*gap < max(match, mismatch)), else
+ * NW_EINVAL. */
+int nw_band_labels(int32_t npairs, const int32_t *scores, const int32_t *a_len,
+                   const int32_t *b_len, nw_scoring sc, int32_t *w_cert, float *target,
+                   void *stream);
+
+/* Workspace for nw_mlp_train_step / nw_mlp_train_epoch at minibatch size
+ * `batch`. */
+int nw_mlp_train_workspace_size(int32_t batch, size_t *bytes);
+
+/* One training step on the minibatch rows[0..batch) of (x, target) (rows:
+ * device int32 indices into x and target; NULL = rows 0..batch-1).  Computes
+ * the mean pinball loss and its gradient, then, when lr > 0, one Adam update
+ * of params (and params_bf16, adam_m, adam_v; mlp->step is incremented).
+ * lr == 0 computes loss and gradient only.  Optional device outputs: *loss
+ * (float32) and grad[NW_MLP_PARAMS] (float32).  batch >= 1; 0 < tau < 1. */
+int nw_mlp_train_step(nw_mlp *mlp, int32_t batch, const float *x, const float *target,
+                      const int32_t *rows, float tau, float lr, float *loss, float *grad,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* One pass over n examples in the order given by order[n] (device int32, a
+ * permutation or any index list; the caller draws it): minibatch b holds
+ * order[b*batch .. min(n, (b+1)*batch)).  losses (device float32
+ * [ceil(n/batch)], may be NULL) gets each minibatch's loss before its update.
+ * lr > 0. */
+int nw_mlp_train_epoch(nw_mlp *mlp, int32_t n, const float *x, const float *target,
+                       const int32_t *order, int32_t batch, float tau, float lr, float *losses,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Learned band: nw_mlp_features, nw_mlp_forward and nw_mlp_widths (with
+ * `margin`) give w_init, then nw_align_batch_banded runs with it.  Same
+ * arguments and outputs as nw_align_batch_banded otherwise; scores and paths
+ * equal nw_align_batch's for any model. */
+int nw_align_batch_learned_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags,
+                                          size_t *bytes);
+
+int nw_align_batch_learned(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
+                           const int32_t *a_len, const int64_t *b_off, const int32_t *b_len,
+                           int32_t max_len, nw_scoring sc, uint32_t flags, const nw_mlp *mlp,
+                           float margin, float fallback_frac, int32_t *scores, uint8_t *paths,
+                           const int64_t *path_off, int32_t *path_len, int32_t *w_used,
+                           uint8_t *status, int64_t *cells, void *ws, size_t ws_bytes,
+                           void *stream);
 
 /* Release host-side caches (tuning tables).  Safe to call at any time when
  * no library call is in flight. */

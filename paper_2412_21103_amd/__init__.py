@@ -18,7 +18,9 @@ __all__ = [
     "Scoring", "NWError", "PAPER_SCORING", "lib", "align", "align_batch", "allpairs",
     "align_workspace_size", "batch_workspace_size", "allpairs_workspace_size",
     "declared_functions", "MOVE_D", "MOVE_U", "MOVE_L", "SCORE_ONLY", "profile_begin",
-    "profile_end", "align_batch_banded", "banded_workspace_size",
+    "profile_end", "align_batch_banded", "banded_workspace_size", "Mlp", "MLP_INPUTS",
+    "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_widths", "band_labels", "mlp_train_step",
+    "mlp_train_epoch", "align_batch_learned", "learned_workspace_size",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,6 +32,7 @@ SCORE_ONLY = 0x1
 PAPER_SCORING = (1, -1, -1)
 
 NW_OK, NW_EINVAL, NW_ERANGE, NW_ENOSPC, NW_EDEVICE, NW_ENOTSUP = 0, -1, -2, -3, -4, -5
+MLP_INPUTS, MLP_HIDDEN, MLP_PARAMS = 259, 64, 20865
 
 
 class Scoring(ctypes.Structure):
@@ -38,6 +41,11 @@ class Scoring(ctypes.Structure):
 
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double)]
+
+
+class MlpState(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("params_bf16", ctypes.c_void_p),
+                ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p), ("step", ctypes.c_int64)]
 
 
 class NWError(RuntimeError):
@@ -72,6 +80,19 @@ def lib():
         L.nw_align_batch_banded.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _u32, _vp,
                                             _i32, ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                             _vp, _sz, _vp]
+        _pm = ctypes.POINTER(MlpState)
+        _f = ctypes.c_float
+        L.nw_mlp_sync.argtypes = [_pm, _vp]
+        L.nw_mlp_features.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.nw_mlp_forward.argtypes = [_pm, _i32, _vp, _vp, _vp]
+        L.nw_mlp_widths.argtypes = [_i32, _vp, _vp, _vp, _f, _vp, _vp]
+        L.nw_band_labels.argtypes = [_i32, _vp, _vp, _vp, Scoring, _vp, _vp, _vp]
+        L.nw_mlp_train_workspace_size.argtypes = [_i32, ctypes.POINTER(_sz)]
+        L.nw_mlp_train_step.argtypes = [_pm, _i32, _vp, _vp, _vp, _f, _f, _vp, _vp, _vp, _sz, _vp]
+        L.nw_mlp_train_epoch.argtypes = [_pm, _i32, _vp, _vp, _vp, _i32, _f, _f, _vp, _vp, _sz, _vp]
+        L.nw_align_batch_learned_workspace_size.argtypes = [_i32, _i32, _u32, ctypes.POINTER(_sz)]
+        L.nw_align_batch_learned.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _u32, _pm,
+                                             _f, _f, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
         L.nw_allpairs_workspace_size.argtypes = [_i32, _i32, ctypes.POINTER(_sz)]
         L.nw_allpairs_scores.argtypes = [_i32, _vp, _vp, _vp, _i32, Scoring, _vp, _vp, _sz, _vp]
         L.nw_release_caches.restype = None
@@ -226,6 +247,146 @@ def align_batch_banded(pool: torch.Tensor, a_off: torch.Tensor, a_len: torch.Ten
                                      _ptr(path_off), _ptr(plen), _ptr(w_used), _ptr(status),
                                      _ptr(cells), _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "nw_align_batch_banded")
+    return scores, paths, path_off, plen, w_used, status, cells
+
+
+def _paths_out(a_len, b_len, npairs, path_off, dev):
+    caps = a_len.to(torch.int64) + b_len.to(torch.int64)
+    if path_off is None:
+        path_off = torch.zeros(npairs, dtype=torch.int64, device=dev)
+        if npairs > 1:
+            path_off[1:] = torch.cumsum(caps, 0)[:-1]
+    total = int((path_off[-1] + caps[-1]).item()) if npairs else 1
+    paths = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+    plen = torch.empty(npairs, dtype=torch.int32, device=dev)
+    return paths, path_off, plen
+
+
+class Mlp:
+    """Band-model state on the device: float32 master weights, their bfloat16
+    copy (int16 bit patterns) and the Adam moments, wrapped in the library's
+    ``nw_mlp`` struct."""
+
+    def __init__(self, params):
+        dev = _dev()
+        p = torch.as_tensor(params, dtype=torch.float32).reshape(-1)
+        if p.numel() != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters, got {p.numel()}")
+        self.params = p.to(dev).contiguous()
+        self.params_bf16 = torch.empty(MLP_PARAMS, dtype=torch.int16, device=dev)
+        self.adam_m = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=dev)
+        self.adam_v = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=dev)
+        self.state = MlpState(self.params.data_ptr(), self.params_bf16.data_ptr(),
+                              self.adam_m.data_ptr(), self.adam_v.data_ptr(), 0)
+        self.sync()
+
+    @property
+    def step(self) -> int:
+        return int(self.state.step)
+
+    def sync(self, stream=None):
+        """Rewrite the bfloat16 copy from the master weights."""
+        _check(lib().nw_mlp_sync(ctypes.byref(self.state), _stream(stream)), "nw_mlp_sync")
+
+
+def mlp_features(pool, a_off, a_len, b_off, b_len, stream=None):
+    """float32 [npairs, 259] feature rows (device)."""
+    npairs = int(a_len.numel())
+    x = torch.empty((npairs, MLP_INPUTS), dtype=torch.float32, device=_dev())
+    _check(lib().nw_mlp_features(npairs, _ptr(pool), _ptr(a_off), _ptr(a_len), _ptr(b_off), _ptr(b_len),
+                                 _ptr(x), _stream(stream)), "nw_mlp_features")
+    return x
+
+
+def mlp_forward(mlp: Mlp, x, stream=None):
+    rows = int(x.shape[0])
+    y = torch.empty(rows, dtype=torch.float32, device=_dev())
+    _check(lib().nw_mlp_forward(ctypes.byref(mlp.state), rows, _ptr(x), _ptr(y), _stream(stream)),
+           "nw_mlp_forward")
+    return y
+
+
+def mlp_widths(yhat, a_len, b_len, margin: float, stream=None):
+    n = int(yhat.numel())
+    w = torch.empty(n, dtype=torch.int32, device=_dev())
+    _check(lib().nw_mlp_widths(n, _ptr(yhat), _ptr(a_len), _ptr(b_len), float(margin), _ptr(w),
+                               _stream(stream)), "nw_mlp_widths")
+    return w
+
+
+def band_labels(scores, a_len, b_len, scoring=PAPER_SCORING, stream=None):
+    """(w_cert int32, target float32 = log1p(w_cert)) device tensors."""
+    n = int(scores.numel())
+    dev = _dev()
+    w = torch.empty(n, dtype=torch.int32, device=dev)
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    _check(lib().nw_band_labels(n, _ptr(scores), _ptr(a_len), _ptr(b_len), _sc(scoring), _ptr(w), _ptr(t),
+                                _stream(stream)), "nw_band_labels")
+    return w, t
+
+
+def mlp_train_workspace_size(batch: int) -> int:
+    out = _sz(0)
+    _check(lib().nw_mlp_train_workspace_size(int(batch), ctypes.byref(out)), "nw_mlp_train_workspace_size")
+    return int(out.value)
+
+
+def mlp_train_step(mlp: Mlp, x, target, tau: float, lr: float, rows=None, want_grad: bool = False,
+                   workspace=None, stream=None):
+    """One step on rows (or all of x).  Returns (loss float32[1], grad float32[P] or None)."""
+    batch = int(rows.numel()) if rows is not None else int(x.shape[0])
+    dev = _dev()
+    ws = _workspace(mlp_train_workspace_size(batch), workspace)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=dev) if want_grad else None
+    _check(lib().nw_mlp_train_step(ctypes.byref(mlp.state), batch, _ptr(x), _ptr(target), _ptr(rows),
+                                   float(tau), float(lr), _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(),
+                                   _stream(stream)), "nw_mlp_train_step")
+    return loss, grad
+
+
+def mlp_train_epoch(mlp: Mlp, x, target, order, batch: int, tau: float, lr: float, workspace=None,
+                    stream=None):
+    """One pass in the given order; returns the per-minibatch losses (device)."""
+    n = int(order.numel())
+    ws = _workspace(mlp_train_workspace_size(batch), workspace)
+    losses = torch.empty(max((n + batch - 1) // batch, 1), dtype=torch.float32, device=_dev())
+    _check(lib().nw_mlp_train_epoch(ctypes.byref(mlp.state), n, _ptr(x), _ptr(target), _ptr(order),
+                                    int(batch), float(tau), float(lr), _ptr(losses), _ptr(ws), ws.numel(),
+                                    _stream(stream)), "nw_mlp_train_epoch")
+    return losses
+
+
+def learned_workspace_size(npairs: int, max_len: int, flags: int = 0) -> int:
+    out = _sz(0)
+    _check(lib().nw_align_batch_learned_workspace_size(int(npairs), int(max_len), int(flags),
+                                                       ctypes.byref(out)),
+           "nw_align_batch_learned_workspace_size")
+    return int(out.value)
+
+
+def align_batch_learned(pool, a_off, a_len, b_off, b_len, max_len: int, mlp: Mlp, margin: float = 0.0,
+                        scoring=PAPER_SCORING, fallback_frac: float = 0.5, score_only: bool = False,
+                        path_off=None, workspace=None, stream=None):
+    """Learned-band batch; same returns as ``align_batch_banded``."""
+    npairs = int(a_len.numel())
+    flags = SCORE_ONLY if score_only else 0
+    dev = _dev()
+    ws = _workspace(learned_workspace_size(npairs, max_len, flags), workspace)
+    scores = torch.empty(npairs, dtype=torch.int32, device=dev)
+    w_used = torch.empty(npairs, dtype=torch.int32, device=dev)
+    status = torch.empty(npairs, dtype=torch.uint8, device=dev)
+    cells = torch.empty(npairs, dtype=torch.int64, device=dev)
+    paths = plen = None
+    if not score_only:
+        paths, path_off, plen = _paths_out(a_len, b_len, npairs, path_off, dev)
+    st = lib().nw_align_batch_learned(npairs, _ptr(pool), _ptr(a_off), _ptr(a_len), _ptr(b_off),
+                                      _ptr(b_len), int(max_len), _sc(scoring), flags,
+                                      ctypes.byref(mlp.state), float(margin), float(fallback_frac),
+                                      _ptr(scores), _ptr(paths), _ptr(path_off), _ptr(plen),
+                                      _ptr(w_used), _ptr(status), _ptr(cells), _ptr(ws), ws.numel(),
+                                      _stream(stream))
+    _check(st, "nw_align_batch_learned")
     return scores, paths, path_off, plen, w_used, status, cells
 
 

@@ -1,0 +1,57 @@
+"""Training driver for the band model (host orchestration of libnw calls).
+
+The labels come from the full-grid method itself: score-only nw_align_batch
+gives each training pair's score S, nw_band_labels turns S into w_cert (the
+smallest half-width the band certificate accepts) and the target
+log1p(w_cert).  Features come from nw_mlp_features; each epoch runs in
+nw_mlp_train_epoch over a seeded permutation drawn here and passed in.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import (PAPER_SCORING, Mlp, align_batch, band_labels, mlp_features, mlp_train_epoch,
+               mlp_train_workspace_size)
+
+
+def he_uniform(seed: int) -> np.ndarray:
+    """He-uniform weights, zero biases, in the library's parameter order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in [(259, 64), (64, 64)]:
+        lim = np.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    parts.append(rng.uniform(-np.sqrt(6.0 / 64), np.sqrt(6.0 / 64), size=64))
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def make_labels(pool, a_off, a_len, b_off, b_len, max_len, scoring=PAPER_SCORING):
+    """Full-grid scores, then (w_cert, target) for every pair (device tensors)."""
+    scores, _, _, _ = align_batch(pool, a_off, a_len, b_off, b_len, max_len, scoring, score_only=True)
+    w_cert, target = band_labels(scores, a_len, b_len, scoring)
+    return scores, w_cert, target
+
+
+def train(x: torch.Tensor, target: torch.Tensor, epochs: int = 200, batch: int = 256,
+          lr: float = 3e-3, tau: float = 0.9, seed: int = 0, init_seed: int = 0, mlp: Mlp | None = None):
+    """Train on (x, target) for `epochs` passes.  Returns (mlp, per-epoch mean loss)."""
+    n = int(x.shape[0])
+    mlp = mlp if mlp is not None else Mlp(he_uniform(init_seed))
+    rng = np.random.default_rng(seed)
+    ws = torch.empty(mlp_train_workspace_size(batch), dtype=torch.uint8, device=x.device)
+    history = []
+    for _ in range(epochs):
+        order = torch.from_numpy(rng.permutation(n).astype(np.int32)).to(x.device)
+        losses = mlp_train_epoch(mlp, x, target, order, batch, tau, lr, workspace=ws)
+        history.append(losses)
+    torch.cuda.synchronize()
+    return mlp, [float(h.mean().item()) for h in history]
+
+
+def features_and_labels(pool, a_off, a_len, b_off, b_len, max_len, scoring=PAPER_SCORING):
+    x = mlp_features(pool, a_off, a_len, b_off, b_len)
+    scores, w_cert, target = make_labels(pool, a_off, a_len, b_off, b_len, max_len, scoring)
+    return x, scores, w_cert, target

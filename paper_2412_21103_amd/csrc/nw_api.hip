@@ -284,24 +284,14 @@ int nw_align_batch_banded_workspace_size(int32_t npairs, int32_t max_len, uint32
     return NW_OK;
 }
 
-int nw_align_batch_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
-                          const int32_t* a_len, const int64_t* b_off, const int32_t* b_len,
-                          int32_t max_len, nw_scoring sc, uint32_t flags, const int32_t* w_init,
-                          int32_t w_default, float fallback_frac, int32_t* scores, uint8_t* paths,
-                          const int64_t* path_off, int32_t* path_len, int32_t* w_used,
-                          uint8_t* status, int64_t* cells, void* ws, size_t ws_bytes, void* stream) {
-    if (npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY) || w_default < 0) return NW_EINVAL;
-    if (!(fallback_frac > 0.f) || fallback_frac > 64.f) return NW_EINVAL;
-    const bool dirs = !(flags & NW_SCORE_ONLY);
-    int st = check_lengths(max_len, max_len, sc);
-    if (st) return st;
-    if ((st = check_scoring(sc, dirs))) return st;
-    if (npairs == 0) return NW_OK;
-    if (!pool || !a_off || !a_len || !b_off || !b_len || !scores || !ws) return NW_EINVAL;
-    if (dirs && (!paths || !path_off || !path_len)) return NW_EINVAL;
-    DeviceInfo di;
-    if ((st = device_info(&di))) return st;
+static int run_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
+                      const int64_t* b_off, const int32_t* b_len, int32_t max_len, nw_scoring sc,
+                      uint32_t flags, const int32_t* w_init, int32_t w_default, float fallback_frac,
+                      int32_t* scores, uint8_t* paths, const int64_t* path_off, int32_t* path_len,
+                      int32_t* w_used, uint8_t* status, int64_t* cells, void* ws, size_t ws_bytes,
+                      hipStream_t stream, const DeviceInfo& di) {
     BatchJob J{};
+    const bool dirs = !(flags & NW_SCORE_ONLY);
     J.allpairs = false;
     J.njobs = npairs;
     J.pool = pool;
@@ -323,7 +313,189 @@ int nw_align_batch_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_
     J.w_used = w_used;
     J.status = status;
     J.cells = cells;
-    return launch_batch(J, ws, ws_bytes, (hipStream_t)stream, di);
+    return launch_batch(J, ws, ws_bytes, stream, di);
+}
+
+// Host checks shared by the banded and learned entry points.
+static int check_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
+                        const int64_t* b_off, const int32_t* b_len, int32_t max_len, nw_scoring sc,
+                        uint32_t flags, float fallback_frac, const int32_t* scores, const uint8_t* paths,
+                        const int64_t* path_off, const int32_t* path_len, const void* ws) {
+    if (npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    if (!(fallback_frac > 0.f) || fallback_frac > 64.f) return NW_EINVAL;
+    const bool dirs = !(flags & NW_SCORE_ONLY);
+    int st = check_lengths(max_len, max_len, sc);
+    if (st) return st;
+    if ((st = check_scoring(sc, dirs))) return st;
+    if (npairs == 0) return NW_OK;
+    if (!pool || !a_off || !a_len || !b_off || !b_len || !scores || !ws) return NW_EINVAL;
+    if (dirs && (!paths || !path_off || !path_len)) return NW_EINVAL;
+    return NW_OK;
+}
+
+int nw_align_batch_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
+                          const int32_t* a_len, const int64_t* b_off, const int32_t* b_len,
+                          int32_t max_len, nw_scoring sc, uint32_t flags, const int32_t* w_init,
+                          int32_t w_default, float fallback_frac, int32_t* scores, uint8_t* paths,
+                          const int64_t* path_off, int32_t* path_len, int32_t* w_used,
+                          uint8_t* status, int64_t* cells, void* ws, size_t ws_bytes, void* stream) {
+    if (w_default < 0) return NW_EINVAL;
+    int st = check_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, fallback_frac,
+                          scores, paths, path_off, path_len, ws);
+    if (st || npairs == 0) return st;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    return run_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, w_init, w_default,
+                      fallback_frac, scores, paths, path_off, path_len, w_used, status, cells, ws, ws_bytes,
+                      (hipStream_t)stream, di);
+}
+
+// ------------------------------------------------------------- band model
+
+static bool mlp_ok(const nw_mlp* mlp, bool training) {
+    return mlp && mlp->params && mlp->params_bf16 && (!training || (mlp->adam_m && mlp->adam_v)) &&
+           mlp->step >= 0;
+}
+
+int nw_mlp_sync(const nw_mlp* mlp, void* stream) {
+    if (!mlp_ok(mlp, false)) return NW_EINVAL;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    return launch_quantize(mlp->params, mlp->params_bf16, (hipStream_t)stream);
+}
+
+int nw_mlp_features(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
+                    const int64_t* b_off, const int32_t* b_len, float* x, void* stream) {
+    if (npairs < 0) return NW_EINVAL;
+    if (npairs == 0) return NW_OK;
+    if (!pool || !a_off || !a_len || !b_off || !b_len || !x) return NW_EINVAL;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    return launch_features(npairs, pool, a_off, a_len, b_off, b_len, x, (hipStream_t)stream);
+}
+
+int nw_mlp_forward(const nw_mlp* mlp, int32_t rows, const float* x, float* yhat, void* stream) {
+    if (rows < 0 || !mlp_ok(mlp, false)) return NW_EINVAL;
+    if (rows == 0) return NW_OK;
+    if (!x || !yhat) return NW_EINVAL;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    return launch_mlp_forward(rows, x, mlp->params, mlp->params_bf16, yhat, (hipStream_t)stream, di);
+}
+
+int nw_mlp_widths(int32_t npairs, const float* yhat, const int32_t* a_len, const int32_t* b_len,
+                  float margin, int32_t* w, void* stream) {
+    if (npairs < 0 || !(margin >= 0.f) || margin > 1e6f) return NW_EINVAL;
+    if (npairs == 0) return NW_OK;
+    if (!yhat || !a_len || !b_len || !w) return NW_EINVAL;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    return launch_widths(npairs, yhat, a_len, b_len, margin, w, (hipStream_t)stream);
+}
+
+int nw_band_labels(int32_t npairs, const int32_t* scores, const int32_t* a_len, const int32_t* b_len,
+                   nw_scoring sc, int32_t* w_cert, float* target, void* stream) {
+    if (npairs < 0) return NW_EINVAL;
+    int st = check_scoring(sc, false);
+    if (st) return st;
+    const int32_t cd = std::max(sc.match, sc.mismatch);
+    if (!(2 * (int64_t)sc.gap < cd)) return NW_EINVAL;
+    if (npairs == 0) return NW_OK;
+    if (!scores || !a_len || !b_len || (!w_cert && !target)) return NW_EINVAL;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    return launch_band_labels(npairs, scores, a_len, b_len, cd, sc.gap, w_cert, target, (hipStream_t)stream);
+}
+
+int nw_mlp_train_workspace_size(int32_t batch, size_t* bytes) {
+    if (!bytes || batch < 1) return NW_EINVAL;
+    *bytes = mlp_train_workspace_bytes(batch);
+    return NW_OK;
+}
+
+static int check_train(const nw_mlp* mlp, int32_t batch, const float* x, const float* target, float tau,
+                       float lr, const void* ws, size_t ws_bytes) {
+    if (!mlp_ok(mlp, lr > 0.f) || batch < 1 || !x || !target || !ws) return NW_EINVAL;
+    if (!(tau > 0.f && tau < 1.f) || !(lr >= 0.f)) return NW_EINVAL;
+    if (ws_bytes < mlp_train_workspace_bytes(batch)) return NW_ENOSPC;
+    return NW_OK;
+}
+
+int nw_mlp_train_step(nw_mlp* mlp, int32_t batch, const float* x, const float* target, const int32_t* rows,
+                      float tau, float lr, float* loss, float* grad, void* ws, size_t ws_bytes,
+                      void* stream) {
+    int st = check_train(mlp, batch, x, target, tau, lr, ws, ws_bytes);
+    if (st) return st;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    return launch_mlp_train_step(mlp, batch, x, target, rows, tau, lr, loss, grad, ws, (hipStream_t)stream,
+                                 di);
+}
+
+int nw_mlp_train_epoch(nw_mlp* mlp, int32_t n, const float* x, const float* target, const int32_t* order,
+                       int32_t batch, float tau, float lr, float* losses, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (n < 0 || !order || !(lr > 0.f)) return NW_EINVAL;
+    int st = check_train(mlp, batch, x, target, tau, lr, ws, ws_bytes);
+    if (st) return st;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    for (int32_t b = 0, i0 = 0; i0 < n; ++b, i0 += batch) {
+        const int32_t rows = std::min(batch, n - i0);
+        st = launch_mlp_train_step(mlp, rows, x, target, order + i0, tau, lr, losses ? losses + b : nullptr,
+                                   nullptr, ws, (hipStream_t)stream, di);
+        if (st) return st;
+    }
+    return NW_OK;
+}
+
+// Learned-band workspace: the banded engine's, then x, yhat and w.
+static size_t learned_extra_bytes(int32_t npairs) {
+    const size_t n = (size_t)std::max(npairs, 1);
+    return align_up(n * NW_MLP_INPUTS * sizeof(float), 256) + align_up(n * sizeof(float), 256) +
+           align_up(n * sizeof(int32_t), 256);
+}
+
+int nw_align_batch_learned_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags, size_t* bytes) {
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    *bytes = align_up(batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di, true),
+                      256) +
+             learned_extra_bytes(npairs);
+    return NW_OK;
+}
+
+int nw_align_batch_learned(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
+                           const int64_t* b_off, const int32_t* b_len, int32_t max_len, nw_scoring sc,
+                           uint32_t flags, const nw_mlp* mlp, float margin, float fallback_frac,
+                           int32_t* scores, uint8_t* paths, const int64_t* path_off, int32_t* path_len,
+                           int32_t* w_used, uint8_t* status, int64_t* cells, void* ws, size_t ws_bytes,
+                           void* stream) {
+    if (!mlp_ok(mlp, false) || !(margin >= 0.f) || margin > 1e6f) return NW_EINVAL;
+    int st = check_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, fallback_frac, scores,
+                          paths, path_off, path_len, ws);
+    if (st || npairs == 0) return st;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    const size_t band_bytes =
+        align_up(batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di, true), 256);
+    if (ws_bytes < band_bytes + learned_extra_bytes(npairs)) return NW_ENOSPC;
+    char* base = (char*)ws + band_bytes;
+    float* x = (float*)base;
+    float* yhat = (float*)(base + align_up((size_t)npairs * NW_MLP_INPUTS * sizeof(float), 256));
+    int32_t* w = (int32_t*)((char*)yhat + align_up((size_t)npairs * sizeof(float), 256));
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = launch_features(npairs, pool, a_off, a_len, b_off, b_len, x, s))) return st;
+    if ((st = launch_mlp_forward(npairs, x, mlp->params, mlp->params_bf16, yhat, s, di))) return st;
+    if ((st = launch_widths(npairs, yhat, a_len, b_len, margin, w, s))) return st;
+    return run_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, w, 0, fallback_frac, scores,
+                      paths, path_off, path_len, w_used, status, cells, ws, band_bytes, s, di);
 }
 
 // -------------------------------------------------------------- all pairs

@@ -224,6 +224,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
         int32_t score;
         bool ok = (m <= A.max_len && n <= A.max_len && m >= 0 && n >= 0);
         int64_t plen = 0;
+        // banded outputs for pairs that never reach the band loop: no band,
+        // no cells (an empty pair counts as solved on the full grid)
+        int32_t w_out = -1;
+        uint32_t st_out = ok ? (0x40u | (A.band_ok ? 0u : 0x80u)) : 0u;
+        int64_t cells_out = 0;
         if (!ok) {
             score = INT32_MIN;
             plen = -1;
@@ -259,13 +264,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
                     if ((int64_t)score > u_out) break;
                     w = max(1, 2 * w);
                 }
-                if (A.w_used) A.w_used[job] = full ? -1 : w;
-                if (A.status) {
-                    const int doublings = min(passes - 1, 31);
-                    A.status[job] = (uint8_t)((passes == 1 && !full ? 1 : 0) | (doublings << 1) |
-                                              (full ? 0x40 : 0) | (A.band_ok ? 0 : 0x80));
-                }
-                if (A.cells) A.cells[job] = cells;
+                w_out = full ? -1 : w;
+                const int doublings = min(passes - 1, 31);
+                st_out = (uint32_t)((passes == 1 && !full ? 1 : 0) | (doublings << 1) | (full ? 0x40 : 0) |
+                                    (A.band_ok ? 0 : 0x80));
+                cells_out = cells;
             } else {
                 const int32_t v = fill_pair<C, DIRS>(A, P.a, P.b, m, n, true, 0, bnd, dirs, lds, &G, &cells);
                 score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
@@ -290,6 +293,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
             A.scores[job] = score;
             if (A.path_len) A.path_len[job] = (int32_t)plen;
             if (A.path_len64) A.path_len64[job] = plen;
+            if constexpr (BANDED) {
+                if (A.w_used) A.w_used[job] = w_out;
+                if (A.status) A.status[job] = (uint8_t)st_out;
+                if (A.cells) A.cells[job] = cells_out;
+            }
         }
     }
 }

@@ -82,4 +82,19 @@ size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const De
 int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t stream,
                  const DeviceInfo& di);
 
+// Band model (nw_mlp.hip).
+int launch_features(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
+                    const int64_t* b_off, const int32_t* b_len, float* x, hipStream_t st);
+int launch_mlp_forward(int32_t rows, const float* x, const float* params, const uint16_t* wq, float* yhat,
+                       hipStream_t st, const DeviceInfo& di);
+int launch_widths(int32_t n, const float* yhat, const int32_t* a_len, const int32_t* b_len, float margin,
+                  int32_t* w, hipStream_t st);
+int launch_band_labels(int32_t n, const int32_t* scores, const int32_t* a_len, const int32_t* b_len,
+                       int32_t cd, int32_t gap, int32_t* w_cert, float* target, hipStream_t st);
+int launch_quantize(const float* params, uint16_t* wq, hipStream_t st);
+size_t mlp_train_workspace_bytes(int32_t batch);
+int launch_mlp_train_step(nw_mlp* mlp, int32_t batch, const float* x, const float* target,
+                          const int32_t* rows_idx, float tau, float lr, float* loss, float* grad_out,
+                          void* ws, hipStream_t st, const DeviceInfo& di);
+
 }  // namespace nw

@@ -66,3 +66,39 @@ def test_host_argument_checks():
                                 vp(0)) == nwp.NW_EINVAL
     assert L.nw_allpairs_scores(70000, vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), vp(1), vp(1),
                                 1, vp(0)) == nwp.NW_ERANGE
+
+
+def test_band_model_host_checks():
+    vp = ctypes.c_void_p
+    L = nwp.lib()
+    P = nwp.Scoring(1, -1, -1)
+    sz = ctypes.c_size_t(0)
+    assert L.nw_mlp_train_workspace_size(0, ctypes.byref(sz)) == nwp.NW_EINVAL
+    assert L.nw_mlp_train_workspace_size(256, ctypes.byref(sz)) == nwp.NW_OK
+    assert sz.value >= (3 * 256 + 4 * 256 * 64 + nwp.MLP_PARAMS) * 4
+    # labels need an applicable certificate: 2*gap < max(match, mismatch)
+    assert L.nw_band_labels(4, vp(1), vp(1), vp(1), nwp.Scoring(1, -1, 1), vp(1), vp(1), vp(0)) == nwp.NW_EINVAL
+    assert L.nw_band_labels(-1, vp(1), vp(1), vp(1), P, vp(1), vp(1), vp(0)) == nwp.NW_EINVAL
+    assert L.nw_band_labels(0, vp(0), vp(0), vp(0), P, vp(0), vp(0), vp(0)) == nwp.NW_OK
+    assert L.nw_band_labels(4, vp(1), vp(1), vp(1), P, vp(0), vp(0), vp(0)) == nwp.NW_EINVAL
+    # missing model arrays, bad tau, bad lr, empty batch, short workspace
+    st = nwp.MlpState(0, 0, 0, 0, 0)
+    assert L.nw_mlp_forward(ctypes.byref(st), 4, vp(1), vp(1), vp(0)) == nwp.NW_EINVAL
+    assert L.nw_mlp_sync(ctypes.byref(st), vp(0)) == nwp.NW_EINVAL
+    ok = nwp.MlpState(1, 1, 1, 1, 0)
+    f = ctypes.c_float
+    step = L.nw_mlp_train_step
+    assert step(ctypes.byref(ok), 8, vp(1), vp(1), vp(0), f(1.0), f(1e-3), vp(0), vp(0), vp(1), 1 << 30, vp(0)) == nwp.NW_EINVAL
+    assert step(ctypes.byref(ok), 8, vp(1), vp(1), vp(0), f(0.9), f(-1.0), vp(0), vp(0), vp(1), 1 << 30, vp(0)) == nwp.NW_EINVAL
+    assert step(ctypes.byref(ok), 0, vp(1), vp(1), vp(0), f(0.9), f(1e-3), vp(0), vp(0), vp(1), 1 << 30, vp(0)) == nwp.NW_EINVAL
+    assert step(ctypes.byref(ok), 8, vp(1), vp(1), vp(0), f(0.9), f(1e-3), vp(0), vp(0), vp(1), 16, vp(0)) == nwp.NW_ENOSPC
+    no_adam = nwp.MlpState(1, 1, 0, 0, 0)
+    assert step(ctypes.byref(no_adam), 8, vp(1), vp(1), vp(0), f(0.9), f(1e-3), vp(0), vp(0), vp(1), 1 << 30, vp(0)) == nwp.NW_EINVAL
+    assert L.nw_mlp_train_epoch(ctypes.byref(ok), 8, vp(1), vp(1), vp(0), 4, f(0.9), f(1e-3), vp(0), vp(1),
+                                1 << 30, vp(0)) == nwp.NW_EINVAL
+    assert L.nw_mlp_widths(4, vp(1), vp(1), vp(1), f(-0.5), vp(1), vp(0)) == nwp.NW_EINVAL
+    assert L.nw_mlp_widths(0, vp(0), vp(0), vp(0), f(0.1), vp(0), vp(0)) == nwp.NW_OK
+    assert L.nw_mlp_features(-2, vp(1), vp(1), vp(1), vp(1), vp(1), vp(1), vp(0)) == nwp.NW_EINVAL
+    assert L.nw_align_batch_learned(4, vp(1), vp(1), vp(1), vp(1), vp(1), 10, P, 0, ctypes.byref(st),
+                                    f(0.1), f(0.5), vp(1), vp(1), vp(1), vp(1), vp(0), vp(0), vp(0),
+                                    vp(1), 1 << 30, vp(0)) == nwp.NW_EINVAL

@@ -118,3 +118,27 @@ def test_band_matches_full_batch(small_band_batch):
     pl = plen.cpu().numpy()
     for k in range(len(pairs)):
         assert paths[k].tolist() == pf[po[k]:po[k] + pl[k]].tolist()
+
+
+def test_band_empty_and_oversize_pairs():
+    rng = np.random.default_rng(79)
+    from workloads import Pairs, random_seq
+    A = [random_seq(rng, m) for m in (0, 5, 0, 300, 40)]
+    B = [random_seq(rng, n) for n in (0, 0, 7, 310, 45)]
+    pairs = Pairs(A, B, "band_edges")
+    ref = [oracle.align(a, b, P) for a, b in zip(A, B)]
+    say("band: empty pairs")
+    s, paths, wu, st, cells = run_band(pairs, np.array([3, 3, 3, 3, 3]))
+    check_equal(pairs, ref, s, paths, "edges")
+    for k in range(3):
+        assert wu[k] == -1 and st[k] == 0x40 and cells[k] == 0, (k, wu[k], st[k], cells[k])
+    # a pair longer than max_len is skipped with status 0
+    pool, ao, al, bo, bl = pack_pairs(pairs)
+    s2, _, _, pl, wu2, st2, cells2 = nwp.align_batch_banded(
+        _dev(pool, np.uint8), _dev(ao, np.int64), _dev(al, np.int32), _dev(bo, np.int64),
+        _dev(bl, np.int32), 100, P, w_default=2)
+    torch.cuda.synchronize()
+    s2, pl, wu2, st2, cells2 = (t.cpu().numpy() for t in (s2, pl, wu2, st2, cells2))
+    assert s2[3] == np.iinfo(np.int32).min and pl[3] == -1
+    assert wu2[3] == -1 and st2[3] == 0 and cells2[3] == 0
+    assert s2[4] == ref[4][0]
