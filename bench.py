@@ -10,6 +10,12 @@ nw_align call (fill + traceback) on inputs already resident in HBM.
 Prints one JSON line: GCUPS (m*n cell updates per second), the fill
 kernel's roofline position (live HIP-event timing of the fill launches in
 the timed region), and the CPU oracle's rate on the same pair.
+
+The same line carries the learned-band batch beside plain full-DP batching
+(`learned_band`): 8192 pairs of lengths 1,000..20,000 at divergence 1..30%,
+the band model trained on 4096 pairs from disjoint seeds (labels from the
+full-DP method), then full-DP and learned-band runs of the whole batch with
+paths, compared for identical scores and paths on the device.
 """
 from __future__ import annotations
 
@@ -48,18 +54,263 @@ def traffic_record():
     return rec.get("hbm_bytes_per_launch")
 
 
+def learned_band(npairs: int, warmup: int, dev, reps: int = 3):
+    """Full-DP batch vs learned certified band on the learned-band workload."""
+    import numpy as np
+    import torch
+
+    import paper_2412_21103_amd as nwp
+    from paper_2412_21103_amd import band_model
+    from workloads import config_band_batch, pack_pairs
+
+    def to_dev(pairs):
+        pool, ao, al, bo, bl = pack_pairs(pairs)
+        t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to(dev)
+        return (t(pool, np.uint8), t(ao, np.int64), t(al, np.int32), t(bo, np.int64), t(bl, np.int32),
+                int(max(al.max(), bl.max())))
+
+    print(f"bench: learned band, generating {npairs} + {npairs // 2} pairs", file=sys.stderr, flush=True)
+    test = to_dev(config_band_batch(npairs=npairs))
+    train = to_dev(config_band_batch(seed=5100, npairs=max(npairs // 2, 1)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, _, _, target = band_model.features_and_labels(*train)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mlp, hist = band_model.train(x, target, epochs=200, batch=256, lr=3e-3, tau=0.9, seed=1)
+    t2 = time.perf_counter()
+    print(f"bench: labels {t1 - t0:.2f} s, training {t2 - t1:.2f} s, loss {hist[0]:.3f} -> {hist[-1]:.4f}",
+          file=sys.stderr, flush=True)
+    del train, x, target
+    cells = float((test[2].to(torch.float64) * test[4].to(torch.float64)).sum())
+    ws = torch.empty(nwp.learned_workspace_size(npairs, test[5]), dtype=torch.uint8, device=dev)
+    margin = 0.1
+
+    def run(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) / reps
+
+    print("bench: full-DP batch", file=sys.stderr, flush=True)
+    ref, t_full = run(lambda: nwp.align_batch(*test, workspace=ws))
+    s_ref, p_ref, poff, plen_ref = ref
+    print("bench: learned-band batch", file=sys.stderr, flush=True)
+    out, t_band = run(lambda: nwp.align_batch_learned(*test, mlp, margin, path_off=poff, workspace=ws))
+    s, p, _, plen, w_used, status, swept = out
+    # identical scores, lengths and every path byte (compared on the device)
+    plen64 = plen_ref.to(torch.int64)
+    starts = torch.repeat_interleave(poff, plen64)
+    base = torch.repeat_interleave(torch.cumsum(plen64, 0) - plen64, plen64)
+    idx = starts + torch.arange(int(plen64.sum()), device=dev) - base
+    exact = bool(torch.equal(s, s_ref) and torch.equal(plen, plen_ref) and torch.equal(p[idx], p_ref[idx]))
+    st = status.cpu().numpy()
+    return {"workload": f"band_batch_{npairs}", "pairs": npairs, "full_equivalent_cells": cells,
+            "full_dp_gcups": round(cells / t_full / 1e9, 1), "full_dp_ms": round(t_full * 1e3, 2),
+            "learned_effective_gcups": round(cells / t_band / 1e9, 1),
+            "learned_computed_gcups": round(float(swept.sum()) / t_band / 1e9, 1),
+            "learned_ms": round(t_band * 1e3, 2), "speedup_vs_full_dp": round(t_full / t_band, 3),
+            "cells_swept_frac": round(float(swept.sum()) / cells, 4),
+            "certified_first_pass": round(float(np.mean(st & 1)), 4),
+            "full_grid_frac": round(float(np.mean((st & 0x40) != 0)), 4), "margin": margin,
+            "train_pairs": max(npairs // 2, 1), "train_s": round(t2 - t1, 3), "label_dp_s": round(t1 - t0, 3),
+            "bit_exact_vs_full_dp": exact}
+
+
+def common_fields(args, value, ms_per_step, config, roofline, cpu, metric_suffix=""):
+    return {
+        "metric": "GCUPS (cell updates/s) full-DP and certified learned-band, 1 MI355X, bit-exact"
+                  + metric_suffix,
+        "value": round(value, 3),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": config,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+
+
+def alu_roofline(kernel, cells, kernel_ms, ops_per_cell):
+    if not kernel_ms:
+        return None
+    achieved = ops_per_cell * cells / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 3),
+            "unit": "T int32 lane-ops/s", "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
+            "kernel": kernel, "kernel_ms": round(kernel_ms, 4), "ops_per_cell": ops_per_cell}
+
+
+def timed_steps(step, args, sync):
+    for _ in range(args.warmup):
+        step()
+    sync()
+    import paper_2412_21103_amd as nwp
+    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
+    nwp.profile_begin()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    sync()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / args.steps, nwp.profile_end()
+
+
+def bench_batch(args):
+    """4096 pairs, m in [100, 2000], 5-15% mutated, scores + paths, one launch per step."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_2412_21103_amd as nwp
+    from workloads import config_batch, pack_pairs
+
+    print("bench: generating the 4096-pair batch", file=sys.stderr, flush=True)
+    pairs = config_batch()
+    pool, ao, al, bo, bl = pack_pairs(pairs)
+    npairs = len(pairs)
+    max_len = int(max(al.max(), bl.max()))
+    cells = int((al.astype(np.int64) * bl.astype(np.int64)).sum())
+    caps = al.astype(np.int64) + bl.astype(np.int64)
+    poff = np.concatenate([[0], np.cumsum(caps)[:-1]]).astype(np.int64)
+    dev = torch.device("cuda", 0)
+    t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to(dev)
+    d = [t(pool, np.uint8), t(ao, np.int64), t(al, np.int32), t(bo, np.int64), t(bl, np.int32)]
+    d_poff = t(poff, np.int64)
+    scores = torch.empty(npairs, dtype=torch.int32, device=dev)
+    paths = torch.empty(int(caps.sum()), dtype=torch.uint8, device=dev)
+    plen = torch.empty(npairs, dtype=torch.int32, device=dev)
+    ws_bytes = nwp.batch_workspace_size(npairs, max_len, 0)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    L = nwp.lib()
+    sc = nwp.Scoring(*nwp.PAPER_SCORING)
+    stream = torch.cuda.current_stream()
+    vp = ctypes.c_void_p
+    ptr = lambda x: vp(x.data_ptr())
+
+    def step():
+        st = L.nw_align_batch(npairs, *[ptr(x) for x in d], max_len, sc, 0, ptr(scores), ptr(paths),
+                              ptr(d_poff), ptr(plen), ptr(ws), ws_bytes, vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_align_batch")
+
+    ms, prof = timed_steps(step, args, torch.cuda.synchronize)
+    k = prof.get("nw_batch")
+    roof = alu_roofline("nw_batch", cells, k[1] / k[0] if k else None, FILL_OPS_PER_CELL)
+    cpu = exact = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nt = oracle.max_threads()
+        print(f"bench: CPU oracle on the whole batch ({nt} threads)", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        s_ref, p_ref = oracle.align_batch(pool, ao, al, bo, bl, oracle.PAPER_SCORING)
+        c1 = time.perf_counter()
+        s_gpu = scores.cpu().numpy()
+        pg, pl = paths.cpu().numpy(), plen.cpu().numpy()
+        exact = bool((s_gpu == s_ref).all() and all(
+            np.array_equal(pg[poff[i]:poff[i] + pl[i]], p_ref[i]) for i in range(npairs)))
+        cpu = {"value": round(cells / (c1 - c0) / 1e9, 4), "unit": "GCUPS", "cores": nt, "kind": "oracle",
+               "sample": f"the whole batch ({cells} cells), scores + paths, full int32 matrix per pair, "
+                         f"OpenMP over pairs, {round(c1 - c0, 2)} s"}
+    config = {"workload": f"batch_{npairs}", "pairs": npairs, "cells": cells, "max_len": max_len,
+              "scoring": list(nwp.PAPER_SCORING), "traceback": True, "bit_exact_vs_oracle": exact}
+    return common_fields(args, cells / (ms * 1e-3) / 1e9, ms, config, roof, cpu)
+
+
+def bench_allpairs(args):
+    """All-pairs score matrix of 512 sequences (lengths 500..5000), score-only."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_2412_21103_amd as nwp
+    from workloads import config_allpairs, pack_seqs
+
+    print("bench: generating the 512 sequences", file=sys.stderr, flush=True)
+    seqs = config_allpairs()
+    pool, off, lens = pack_seqs(seqs)
+    nseq = len(seqs)
+    max_len = int(lens.max())
+    l64 = lens.astype(np.int64)
+    cells = int((l64.sum() ** 2 - (l64 ** 2).sum()) // 2)  # i < j pairs
+    dev = torch.device("cuda", 0)
+    t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to(dev)
+    d = [t(pool, np.uint8), t(off, np.int64), t(lens, np.int32)]
+    out = torch.empty((nseq, nseq), dtype=torch.int32, device=dev)
+    ws_bytes = nwp.allpairs_workspace_size(nseq, max_len)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    L = nwp.lib()
+    sc = nwp.Scoring(*nwp.PAPER_SCORING)
+    stream = torch.cuda.current_stream()
+    vp = ctypes.c_void_p
+    ptr = lambda x: vp(x.data_ptr())
+
+    def step():
+        st = L.nw_allpairs_scores(nseq, *[ptr(x) for x in d], max_len, sc, ptr(out), ptr(ws), ws_bytes,
+                                  vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_allpairs_scores")
+
+    ms, prof = timed_steps(step, args, torch.cuda.synchronize)
+    k = prof.get("nw_allpairs")
+    roof = alu_roofline("nw_allpairs", cells, k[1] / k[0] if k else None, 2)
+    cpu = exact = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nt = oracle.max_threads()
+        ns = 64
+        sub = seqs[:ns]
+        sp, so, sl = pack_seqs(sub)
+        s64 = sl.astype(np.int64)
+        sub_cells = int((s64.sum() ** 2 - (s64 ** 2).sum()) // 2)
+        print(f"bench: CPU oracle on the first {ns} sequences ({nt} threads)", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        M = oracle.allpairs(sp, so, sl, oracle.PAPER_SCORING)
+        c1 = time.perf_counter()
+        exact = bool(np.array_equal(out.cpu().numpy()[:ns, :ns], M))
+        cpu = {"value": round(sub_cells / (c1 - c0) / 1e9, 4), "unit": "GCUPS", "cores": nt, "kind": "oracle",
+               "sample": f"the first {ns} sequences ({ns * (ns - 1) // 2} pairs, {sub_cells} cells), "
+                         f"score-only, OpenMP over pairs, {round(c1 - c0, 2)} s"}
+    config = {"workload": f"allpairs_{nseq}", "sequences": nseq, "pairs": nseq * (nseq - 1) // 2,
+              "cells": cells, "scoring": list(nwp.PAPER_SCORING), "traceback": False,
+              "bit_exact_vs_oracle_sample": exact}
+    return common_fields(args, cells / (ms * 1e-3) / 1e9, ms, config, roof, cpu)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["long_pair", "batch", "allpairs"], default="long_pair")
     ap.add_argument("--length", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-band", action="store_true", help="skip the learned-band batch")
+    ap.add_argument("--band-pairs", type=int, default=8192)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(pairs are independent, see DESIGN.md for how the work would shard)", file=sys.stderr)
         return 2
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return 0
+    if args.workload == "allpairs":
+        print(json.dumps(bench_allpairs(args)), flush=True)
+        return 0
 
     import ctypes
 
@@ -116,9 +367,9 @@ def main():
     gpu_path = path[:k].cpu().numpy()
 
     fill = prof.get("nw_fill_coop")
-    walk = prof.get("nw_walk_single")
     fill_ms = fill[1] / fill[0] if fill else None
-    walk_ms = walk[1] / walk[0] if walk else None
+    tb = [prof[k] for k in ("nw_tb_spec", "nw_tb_fix", "nw_tb_emit") if k in prof]
+    walk_ms = sum(v[1] / v[0] for v in tb) if tb else None
     roofline = None
     if fill_ms:
         achieved = FILL_OPS_PER_CELL * cells / (fill_ms * 1e-3) / 1e12
@@ -141,8 +392,10 @@ def main():
                "sample": f"the whole {m} x {n} pair, score + traceback, two score rows + "
                          f"a direction byte per cell, {round(c1 - c0, 2)} s"}
 
+    band = None if args.no_band else learned_band(args.band_pairs, args.warmup, dev)
+
     out = {
-        "metric": "GCUPS (cell updates/s) full-DP, 1 MI355X, bit-exact",
+        "metric": "GCUPS (cell updates/s) full-DP and certified learned-band, 1 MI355X, bit-exact",
         "value": round(gcups, 3),
         "unit": "GCUPS",
         "n_gpus": 1,
@@ -161,6 +414,7 @@ def main():
                    "bit_exact_vs_oracle": exact},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned_band": band,
     }
     print(json.dumps(out), flush=True)
     return 0

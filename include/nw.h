@@ -68,6 +68,17 @@ enum {
 
 /* Flags. */
 #define NW_SCORE_ONLY 0x1u /* no traceback: paths, path_off, path_len may be NULL */
+/* NW_GRAPH (nw_align_batch, nw_align_batch_banded, nw_align_batch_learned):
+ * the first call with a given set of arguments (every pointer, count, size,
+ * constant, flag and the stream) captures its launches into a HIP graph;
+ * later calls with the same arguments replay that graph, which saves the
+ * per-launch overhead of the planning kernels.  A replay reads every input
+ * in place, so the caller may change the input bytes (not the addresses or
+ * counts) between calls.  The stream must not be the null stream.  When the
+ * caller's stream is already being captured the launches go into the
+ * caller's graph instead.  The library owns the cached graphs (at most 256;
+ * calls beyond that run without a graph) until nw_release_caches(). */
+#define NW_GRAPH 0x2u
 
 /* Human-readable text for a status code (static storage). */
 const char *nw_strerror(int status);
@@ -126,8 +137,12 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  *     c_d = max(match, mismatch)   (valid when 2*gap < c_d),
  * which forces every optimal path inside the band, so score and tie-break
  * path equal the full grid's.  Otherwise w doubles (0 becomes 1).  The full
- * grid is used directly once w >= min(m,n), once the band's height reaches
- * fallback_frac of m, or when 2*gap >= c_d.
+ * grid is used directly once w >= min(m,n), once the band's height
+ * 128 + |D| + 2w reaches fallback_frac of m, or when 2*gap >= c_d.  A first
+ * half-width past the height limit (but below min(m,n)) is first lowered to
+ * the widest band under the limit, so a pair reaches the full grid only after
+ * a band has failed.  Each pass sweeps 128, 256 or 512 columns per wave,
+ * whichever the library's cost model rates fastest for its height.
  *
  * w_init (device int32[npairs], may be NULL: then w_default for all) gives
  * each pair's first half-width, e.g. the band model's prediction.  Optional
@@ -271,8 +286,29 @@ int nw_align_batch_learned(int32_t npairs, const uint8_t *pool, const int64_t *a
                            uint8_t *status, int64_t *cells, void *ws, size_t ws_bytes,
                            void *stream);
 
-/* Release host-side caches (tuning tables).  Safe to call at any time when
- * no library call is in flight. */
+/* ------------------------------------------------------------------------
+ * Autotuner for the batch engine (nw_align_batch, nw_align_batch_banded,
+ * nw_align_batch_learned, nw_allpairs_scores).  Each pass of a pair sweeps
+ * 128, 256 or 512 columns per wave, whichever minimises
+ *     strips x (rows per strip + 64) x step_cost(width)
+ * for its height.  The built-in step costs are instruction counts of the
+ * compiled loops; nw_autotune measures them instead.  It runs the given
+ * sample batch (same description and buffers as nw_align_batch with paths,
+ * paper scoring) with each width forced, with and without directions,
+ * 3 times each, and stores the measured time per strip-row of each width,
+ * normalised to 1000 for 512 columns, as the current device's cost table.
+ * Synchronises `stream`; results of later calls do not depend on the table,
+ * only their speed.  costs (host int32[6], may be NULL) receives the table:
+ * widths 128/256/512 with directions, then score-only.  npairs >= 1.
+ * nw_release_caches() restores the built-in costs.
+ * ------------------------------------------------------------------------ */
+int nw_autotune(int32_t npairs, const uint8_t *pool, const int64_t *a_off, const int32_t *a_len,
+                const int64_t *b_off, const int32_t *b_len, int32_t max_len, int32_t *scores,
+                uint8_t *paths, const int64_t *path_off, int32_t *path_len, void *ws,
+                size_t ws_bytes, int32_t *costs, void *stream);
+
+/* Release host-side caches: the NW_GRAPH graphs and the autotuned cost
+ * tables.  Call only when no library work is in flight on any stream. */
 void nw_release_caches(void);
 
 /* ------------------------------------------------------------------------

@@ -17,10 +17,10 @@ import torch
 __all__ = [
     "Scoring", "NWError", "PAPER_SCORING", "lib", "align", "align_batch", "allpairs",
     "align_workspace_size", "batch_workspace_size", "allpairs_workspace_size",
-    "declared_functions", "MOVE_D", "MOVE_U", "MOVE_L", "SCORE_ONLY", "profile_begin",
+    "declared_functions", "MOVE_D", "MOVE_U", "MOVE_L", "SCORE_ONLY", "GRAPH", "profile_begin",
     "profile_end", "align_batch_banded", "banded_workspace_size", "Mlp", "MLP_INPUTS",
     "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_widths", "band_labels", "mlp_train_step",
-    "mlp_train_epoch", "align_batch_learned", "learned_workspace_size",
+    "mlp_train_epoch", "align_batch_learned", "learned_workspace_size", "autotune",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,6 +29,7 @@ _HEADER = os.path.join(os.path.dirname(_HERE), "include", "nw.h")
 
 MOVE_D, MOVE_U, MOVE_L = 1, 2, 3
 SCORE_ONLY = 0x1
+GRAPH = 0x2
 PAPER_SCORING = (1, -1, -1)
 
 NW_OK, NW_EINVAL, NW_ERANGE, NW_ENOSPC, NW_EDEVICE, NW_ENOTSUP = 0, -1, -2, -3, -4, -5
@@ -93,6 +94,7 @@ def lib():
         L.nw_align_batch_learned_workspace_size.argtypes = [_i32, _i32, _u32, ctypes.POINTER(_sz)]
         L.nw_align_batch_learned.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _u32, _pm,
                                              _f, _f, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.nw_autotune.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp, _vp]
         L.nw_allpairs_workspace_size.argtypes = [_i32, _i32, ctypes.POINTER(_sz)]
         L.nw_allpairs_scores.argtypes = [_i32, _vp, _vp, _vp, _i32, Scoring, _vp, _vp, _sz, _vp]
         L.nw_release_caches.restype = None
@@ -388,6 +390,21 @@ def align_batch_learned(pool, a_off, a_len, b_off, b_len, max_len: int, mlp: Mlp
                                       _stream(stream))
     _check(st, "nw_align_batch_learned")
     return scores, paths, path_off, plen, w_used, status, cells
+
+
+def autotune(pool, a_off, a_len, b_off, b_len, max_len: int, stream=None):
+    """Measure the sweep-width costs on a sample batch (synchronises); returns
+    the table {"dirs": [c128, c256, c512], "score": [...]}."""
+    npairs = int(a_len.numel())
+    dev = _dev()
+    ws = _workspace(batch_workspace_size(npairs, max_len, 0), None)
+    scores = torch.empty(npairs, dtype=torch.int32, device=dev)
+    paths, path_off, plen = _paths_out(a_len, b_len, npairs, None, dev)
+    costs = (ctypes.c_int32 * 6)()
+    _check(lib().nw_autotune(npairs, _ptr(pool), _ptr(a_off), _ptr(a_len), _ptr(b_off), _ptr(b_len),
+                             int(max_len), _ptr(scores), _ptr(paths), _ptr(path_off), _ptr(plen), _ptr(ws),
+                             ws.numel(), costs, _stream(stream)), "nw_autotune")
+    return {"dirs": list(costs[:3]), "score": list(costs[3:])}
 
 
 def allpairs(pool: torch.Tensor, off: torch.Tensor, lens: torch.Tensor, max_len: int,

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -78,6 +80,8 @@ hipEvent_t prof_event() {
 ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), st(s), slot(-1) {
     ProfState& P = prof();
     if (!P.on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     hipEvent_t e = prof_event();
     if (!e) return;
     slot = (int)P.used - 1;
@@ -91,6 +95,72 @@ ProfScope::~ProfScope() {
     if (!e) return;
     (void)hipEventRecord(e, st);
     P.marks.emplace_back(name, slot);
+}
+
+// ---- NW_GRAPH: captured launch sequences keyed by the call's arguments ----
+
+namespace {
+constexpr size_t kMaxGraphs = 256;
+struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+};
+struct GraphCache {
+    std::mutex mu;
+    std::vector<GraphEntry> entries;
+};
+GraphCache& graphs() {
+    static GraphCache c;
+    return c;
+}
+}  // namespace
+
+std::vector<uint64_t> graph_key(std::initializer_list<uint64_t> words) { return std::vector<uint64_t>(words); }
+
+// Run `launch` (which queues this call's kernels on st) directly, or through
+// a cached graph when `use` is set.
+template <class F>
+int with_graph(bool use, std::vector<uint64_t> key, hipStream_t st, F&& launch) {
+    if (!use) return launch();
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return NW_EDEVICE;
+    if (cs != hipStreamCaptureStatusNone) return launch();  // recorded into the caller's graph
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return NW_EDEVICE;
+    key.push_back((uint64_t)(uintptr_t)st);
+    key.push_back((uint64_t)dev);
+    GraphCache& C = graphs();
+    std::lock_guard<std::mutex> lock(C.mu);
+    for (const GraphEntry& e : C.entries)
+        if (e.key == key) return hipGraphLaunch(e.exec, st) == hipSuccess ? NW_OK : NW_EDEVICE;
+    if (C.entries.size() >= kMaxGraphs) return launch();
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return NW_EDEVICE;
+    const int r = launch();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (r != NW_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r != NW_OK ? r : NW_EDEVICE;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return NW_EDEVICE;
+    C.entries.push_back(GraphEntry{std::move(key), exec});
+    return hipGraphLaunch(exec, st) == hipSuccess ? NW_OK : NW_EDEVICE;
+}
+
+void release_graphs() {
+    GraphCache& C = graphs();
+    std::lock_guard<std::mutex> lock(C.mu);
+    for (GraphEntry& e : C.entries) (void)hipGraphExecDestroy(e.exec);
+    C.entries.clear();
+}
+
+static uint64_t w(const void* p) { return (uint64_t)(uintptr_t)p; }
+static uint64_t w(int64_t v) { return (uint64_t)v; }
+static uint64_t wsc(const nw_scoring& sc) {
+    return ((uint64_t)(uint32_t)sc.match << 32) ^ ((uint64_t)(uint32_t)sc.mismatch << 16) ^ (uint32_t)sc.gap;
 }
 
 }  // namespace nw
@@ -113,7 +183,10 @@ const char* nw_strerror(int status) {
 
 int nw_version(void) { return 100; }
 
-void nw_release_caches(void) {}
+void nw_release_caches(void) {
+    release_graphs();
+    reset_step_costs();
+}
 
 int nw_profile_begin(void) {
     ProfState& P = prof();
@@ -231,7 +304,7 @@ int nw_align(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, nw_scorin
 // ------------------------------------------------------------------ batch
 
 int nw_align_batch_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags, size_t* bytes) {
-    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH))) return NW_EINVAL;
     DeviceInfo di;
     int st = device_info(&di);
     if (st) return st;
@@ -244,7 +317,8 @@ int nw_align_batch(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
                    int32_t max_len, nw_scoring sc, uint32_t flags, int32_t* scores,
                    uint8_t* paths, const int64_t* path_off, int32_t* path_len, void* ws,
                    size_t ws_bytes, void* stream) {
-    if (npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    if (npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH))) return NW_EINVAL;
+    if ((flags & NW_GRAPH) && !stream) return NW_EINVAL;
     const bool dirs = !(flags & NW_SCORE_ONLY);
     int st = check_lengths(max_len, max_len, sc);
     if (st) return st;
@@ -269,18 +343,99 @@ int nw_align_batch(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
     J.paths = paths;
     J.path_off = path_off;
     J.path_len = dirs ? path_len : nullptr;
-    return launch_batch(J, ws, ws_bytes, (hipStream_t)stream, di);
+    hipStream_t s = (hipStream_t)stream;
+    return with_graph((flags & NW_GRAPH) != 0,
+                      graph_key({1, w((int64_t)npairs), w(pool), w(a_off), w(a_len), w(b_off), w(b_len),
+                                 w((int64_t)max_len), wsc(sc), w((int64_t)flags), w(scores), w(paths),
+                                 w(path_off), w(path_len), w(ws), w((int64_t)ws_bytes)}),
+                      s, [&] { return launch_batch(J, ws, ws_bytes, s, di); });
+}
+
+// -------------------------------------------------------------- autotuner
+
+int nw_autotune(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
+                const int64_t* b_off, const int32_t* b_len, int32_t max_len, int32_t* scores, uint8_t* paths,
+                const int64_t* path_off, int32_t* path_len, void* ws, size_t ws_bytes, int32_t* costs,
+                void* stream) {
+    if (npairs < 1 || max_len < 1) return NW_EINVAL;
+    const nw_scoring sc{1, -1, -1};
+    int st = check_lengths(max_len, max_len, sc);
+    if (st) return st;
+    if (!pool || !a_off || !a_len || !b_off || !b_len || !scores || !paths || !path_off || !path_len || !ws)
+        return NW_EINVAL;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    if (ws_bytes < batch_workspace_bytes(1, max_len, true, di)) return NW_ENOSPC;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> ml(npairs), nl(npairs);
+    if (hipMemcpyAsync(ml.data(), a_len, (size_t)npairs * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(nl.data(), b_len, (size_t)npairs * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return NW_EDEVICE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return NW_EDEVICE;
+    int32_t table[2][3];
+    int rc = NW_OK;
+    for (int dirs = 1; dirs >= 0 && rc == NW_OK; --dirs) {
+        double per_unit[3];
+        for (int c = 0; c < 3 && rc == NW_OK; ++c) {
+            const int C = 2 << c;
+            const int64_t cols = 64 * C;
+            double units = 0;  // sum over pairs of strips x (rows + ramp)
+            for (int32_t k = 0; k < npairs; ++k)
+                if (ml[k] > 0 && nl[k] > 0 && ml[k] <= max_len && nl[k] <= max_len)
+                    units += (double)((nl[k] + cols - 1) / cols) * (double)(ml[k] + 64);
+            BatchJob J{};
+            J.njobs = npairs;
+            J.pool = pool;
+            J.a_off = a_off;
+            J.a_len = a_len;
+            J.b_off = b_off;
+            J.b_len = b_len;
+            J.max_len = max_len;
+            J.sc = sc;
+            J.dirs = dirs != 0;
+            J.scores = scores;
+            J.paths = paths;
+            J.path_off = path_off;
+            J.path_len = dirs ? path_len : nullptr;
+            J.force_cols = C;
+            float best = 1e30f;
+            for (int rep = 0; rep < 3 && rc == NW_OK; ++rep) {
+                if (hipEventRecord(e0, s) != hipSuccess) rc = NW_EDEVICE;
+                if (rc == NW_OK) rc = launch_batch(J, ws, ws_bytes, s, di);
+                float ms = 0.f;
+                if (rc == NW_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = NW_EDEVICE;
+                if (rep > 0) best = std::min(best, ms);  // the first run warms up
+            }
+            per_unit[c] = units > 0 ? (double)best / units : 1.0;
+        }
+        for (int c = 0; c < 3; ++c)
+            table[dirs][c] = (int32_t)std::max(1.0, std::min(1e5, 1000.0 * per_unit[c] / per_unit[2]));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != NW_OK) return rc;
+    set_step_costs(di.device, table[1], table[0]);
+    if (costs)
+        for (int c = 0; c < 3; ++c) {
+            costs[c] = table[1][c];
+            costs[3 + c] = table[0][c];
+        }
+    return NW_OK;
 }
 
 // ---------------------------------------------------------- certified band
 
 int nw_align_batch_banded_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags,
                                          size_t* bytes) {
-    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH))) return NW_EINVAL;
     DeviceInfo di;
     int st = device_info(&di);
     if (st) return st;
-    *bytes = batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di, true);
+    *bytes = batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di);
     return NW_OK;
 }
 
@@ -320,8 +475,10 @@ static int run_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
 static int check_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
                         const int64_t* b_off, const int32_t* b_len, int32_t max_len, nw_scoring sc,
                         uint32_t flags, float fallback_frac, const int32_t* scores, const uint8_t* paths,
-                        const int64_t* path_off, const int32_t* path_len, const void* ws) {
-    if (npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+                        const int64_t* path_off, const int32_t* path_len, const void* ws,
+                        bool ws_stream_ok) {
+    if (npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH))) return NW_EINVAL;
+    if ((flags & NW_GRAPH) && !ws_stream_ok) return NW_EINVAL;
     if (!(fallback_frac > 0.f) || fallback_frac > 64.f) return NW_EINVAL;
     const bool dirs = !(flags & NW_SCORE_ONLY);
     int st = check_lengths(max_len, max_len, sc);
@@ -341,13 +498,21 @@ int nw_align_batch_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_
                           uint8_t* status, int64_t* cells, void* ws, size_t ws_bytes, void* stream) {
     if (w_default < 0) return NW_EINVAL;
     int st = check_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, fallback_frac,
-                          scores, paths, path_off, path_len, ws);
+                          scores, paths, path_off, path_len, ws, stream != nullptr);
     if (st || npairs == 0) return st;
     DeviceInfo di;
     if ((st = device_info(&di))) return st;
-    return run_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, w_init, w_default,
-                      fallback_frac, scores, paths, path_off, path_len, w_used, status, cells, ws, ws_bytes,
-                      (hipStream_t)stream, di);
+    hipStream_t s = (hipStream_t)stream;
+    return with_graph((flags & NW_GRAPH) != 0,
+                      graph_key({2, w((int64_t)npairs), w(pool), w(a_off), w(a_len), w(b_off), w(b_len),
+                                 w((int64_t)max_len), wsc(sc), w((int64_t)flags), w(w_init), w((int64_t)w_default),
+                                 w((int64_t)(fallback_frac * 1048576.f)), w(scores), w(paths), w(path_off),
+                                 w(path_len), w(w_used), w(status), w(cells), w(ws), w((int64_t)ws_bytes)}),
+                      s, [&] {
+                          return run_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, w_init,
+                                            w_default, fallback_frac, scores, paths, path_off, path_len, w_used,
+                                            status, cells, ws, ws_bytes, s, di);
+                      });
 }
 
 // ------------------------------------------------------------- band model
@@ -461,11 +626,11 @@ static size_t learned_extra_bytes(int32_t npairs) {
 }
 
 int nw_align_batch_learned_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags, size_t* bytes) {
-    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~NW_SCORE_ONLY)) return NW_EINVAL;
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH))) return NW_EINVAL;
     DeviceInfo di;
     int st = device_info(&di);
     if (st) return st;
-    *bytes = align_up(batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di, true),
+    *bytes = align_up(batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di),
                       256) +
              learned_extra_bytes(npairs);
     return NW_OK;
@@ -479,23 +644,32 @@ int nw_align_batch_learned(int32_t npairs, const uint8_t* pool, const int64_t* a
                            void* stream) {
     if (!mlp_ok(mlp, false) || !(margin >= 0.f) || margin > 1e6f) return NW_EINVAL;
     int st = check_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, fallback_frac, scores,
-                          paths, path_off, path_len, ws);
+                          paths, path_off, path_len, ws, stream != nullptr);
     if (st || npairs == 0) return st;
     DeviceInfo di;
     if ((st = device_info(&di))) return st;
     const size_t band_bytes =
-        align_up(batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di, true), 256);
+        align_up(batch_workspace_bytes(npairs, std::max(max_len, 1), !(flags & NW_SCORE_ONLY), di), 256);
     if (ws_bytes < band_bytes + learned_extra_bytes(npairs)) return NW_ENOSPC;
     char* base = (char*)ws + band_bytes;
     float* x = (float*)base;
     float* yhat = (float*)(base + align_up((size_t)npairs * NW_MLP_INPUTS * sizeof(float), 256));
-    int32_t* w = (int32_t*)((char*)yhat + align_up((size_t)npairs * sizeof(float), 256));
+    int32_t* wv = (int32_t*)((char*)yhat + align_up((size_t)npairs * sizeof(float), 256));
     hipStream_t s = (hipStream_t)stream;
-    if ((st = launch_features(npairs, pool, a_off, a_len, b_off, b_len, x, s))) return st;
-    if ((st = launch_mlp_forward(npairs, x, mlp->params, mlp->params_bf16, yhat, s, di))) return st;
-    if ((st = launch_widths(npairs, yhat, a_len, b_len, margin, w, s))) return st;
-    return run_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, w, 0, fallback_frac, scores,
-                      paths, path_off, path_len, w_used, status, cells, ws, band_bytes, s, di);
+    return with_graph(
+        (flags & NW_GRAPH) != 0,
+        graph_key({3, w((int64_t)npairs), w(pool), w(a_off), w(a_len), w(b_off), w(b_len), w((int64_t)max_len),
+                   wsc(sc), w((int64_t)flags), w(mlp->params), w(mlp->params_bf16),
+                   w((int64_t)(margin * 1048576.f)), w((int64_t)(fallback_frac * 1048576.f)), w(scores), w(paths),
+                   w(path_off), w(path_len), w(w_used), w(status), w(cells), w(ws), w((int64_t)ws_bytes)}),
+        s, [&] {
+            int r;
+            if ((r = launch_features(npairs, pool, a_off, a_len, b_off, b_len, x, s))) return r;
+            if ((r = launch_mlp_forward(npairs, x, mlp->params, mlp->params_bf16, yhat, s, di))) return r;
+            if ((r = launch_widths(npairs, yhat, a_len, b_len, margin, wv, s))) return r;
+            return run_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, wv, 0, fallback_frac,
+                              scores, paths, path_off, path_len, w_used, status, cells, ws, band_bytes, s, di);
+        });
 }
 
 // -------------------------------------------------------------- all pairs

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "nw_internal.h"
 #include "nw_strip.h"
@@ -37,6 +38,10 @@ struct KArgs {
     const int32_t* b_len;
     int32_t max_len;
     int32_t kdm, kdx, gap;
+    // per-step cost of a sweep with C = 2, 4, 8 columns per lane (relative
+    // units); the engine picks, per pair and pass, the width whose strips x
+    // (rows + ramp) x step cost is smallest
+    int32_t step_cost[3];
     int32_t* scores;
     uint8_t* paths;
     const int64_t* path_off;
@@ -197,9 +202,50 @@ __device__ __forceinline__ int32_t fill_pair(const KArgs& A, const uint8_t* pa, 
     return __builtin_amdgcn_readlane(vlast, lsel);
 }
 
-template <int C, bool DIRS, bool ALLPAIRS, bool BANDED>
+// Band height (rows per strip) of band(w) for a C-column sweep.
+__device__ __forceinline__ int band_height(int C, int m, int n, int w) {
+    const int dlt = n > m ? n - m : m - n;
+    return (int)min((int64_t)m, (int64_t)kWave * C + dlt + 2 * (int64_t)w);
+}
+
+// Sweep width for one pass (the full grid, or band(w)): the C in {2, 4, 8}
+// with the least modelled time, strips x (rows per strip + ramp) x step cost.
+__device__ __forceinline__ int pick_cols(const KArgs& A, int m, int n, bool full, int w) {
+    int best = 2;
+    int64_t best_cost = INT64_MAX;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int C = 2 << c;
+        const int64_t strips = (n + kWave * C - 1) / (kWave * C);
+        const int height = full ? m : band_height(C, m, n, w);
+        const int64_t cost = strips * (int64_t)(height + kWave) * A.step_cost[c];
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = C;
+        }
+    }
+    return best;
+}
+
+template <bool DIRS>
+__device__ __forceinline__ int32_t fill_any(int C, const KArgs& A, const uint8_t* pa, const uint8_t* pb, int m,
+                                            int n, bool full, int w, int32_t* bnd, uint32_t* dirs,
+                                            uint32_t* lds, int* G, int64_t* cells) {
+    if (C == 8) return fill_pair<8, DIRS>(A, pa, pb, m, n, full, w, bnd, dirs, lds, G, cells);
+    if (C == 4) return fill_pair<4, DIRS>(A, pa, pb, m, n, full, w, bnd, dirs, lds, G, cells);
+    return fill_pair<2, DIRS>(A, pa, pb, m, n, full, w, bnd, dirs, lds, G, cells);
+}
+
+__device__ __forceinline__ int64_t walk_any(int C, const uint32_t* dirs, int m, int n, int G, uint32_t* lds,
+                                            uint8_t* rev, int band_hi) {
+    if (C == 8) return walk_back<8>(dirs, m, n, G, lds, rev, band_hi);
+    if (C == 4) return walk_back<4>(dirs, m, n, G, lds, rev, band_hi);
+    return walk_back<2>(dirs, m, n, G, lds, rev, band_hi);
+}
+
+template <bool DIRS, bool ALLPAIRS, bool BANDED>
 __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
-    __shared__ uint32_t smem[kWavesPerBlock][StripShape<C>::kLdsWords];
+    __shared__ uint32_t smem[kWavesPerBlock][StripShape<8>::kLdsWords];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
     uint32_t* lds = smem[wave];
@@ -207,7 +253,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
     int32_t* bnd = A.bnd + slot * A.bnd_stride;
     uint32_t* dirs = DIRS ? A.dirs + slot * A.dirs_stride : nullptr;
     uint8_t* rev = DIRS ? A.rev + slot * A.rev_stride : nullptr;
-    constexpr int kCols = kWave * C;
 
     // The job loop keeps every lane active on every path: the queue ticket
     // comes from an atomic that all lanes execute (lane 0 adds 1, the others
@@ -245,7 +290,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
             int64_t cells = 0;
             bool full = true;
             int w = 0;
-            int passes = 0;
+            int C = 8;
             if constexpr (BANDED) {
                 // certified band: double w until the region score beats the best
                 // score any path leaving band(w) can reach, or the band is so
@@ -253,10 +298,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
                 w = max(0, A.w_init ? A.w_init[job] : A.w_default);
                 const int mn = min(m, n);
                 const int64_t dlt = n > m ? n - m : m - n;
+                // the fallback test uses the narrowest sweep's band height:
+                // full grid once 128 + |D| + 2w >= frac * m.  A first width
+                // beyond that is first tried at the widest band below it, so
+                // only a failed band sends a pair to the full grid.
+                const int64_t fb_num = (int64_t)A.frac_1024 * m - 1024 * (2 * kWave + dlt) - 1;
+                const int64_t w_fb = fb_num >= 0 ? fb_num / 2048 : -1;
+                if (w < mn && w_fb >= 0 && w > w_fb) w = (int)w_fb;
+                int passes = 0;
                 for (;;) {
                     full = !A.band_ok || w >= mn ||
-                           (int64_t)(kCols + dlt + 2 * (int64_t)w) * 1024 >= (int64_t)A.frac_1024 * m;
-                    const int32_t v = fill_pair<C, DIRS>(A, P.a, P.b, m, n, full, w, bnd, dirs, lds, &G, &cells);
+                           (int64_t)(2 * kWave + dlt + 2 * (int64_t)w) * 1024 >= (int64_t)A.frac_1024 * m;
+                    C = uniform(pick_cols(A, m, n, full, w));
+                    const int32_t v = fill_any<DIRS>(C, A, P.a, P.b, m, n, full, w, bnd, dirs, lds, &G, &cells);
                     ++passes;
                     score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
                     if (full) break;
@@ -270,12 +324,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
                                     (A.band_ok ? 0 : 0x80));
                 cells_out = cells;
             } else {
-                const int32_t v = fill_pair<C, DIRS>(A, P.a, P.b, m, n, true, 0, bnd, dirs, lds, &G, &cells);
+                C = uniform(pick_cols(A, m, n, true, 0));
+                const int32_t v = fill_any<DIRS>(C, A, P.a, P.b, m, n, true, 0, bnd, dirs, lds, &G, &cells);
                 score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
             }
             if constexpr (DIRS && !ALLPAIRS) {
                 const int band_hi = full ? (1 << 30) : max(0, n - m) + w;
-                int64_t len = walk_back<C>(dirs, m, n, G, lds, rev, band_hi);
+                int64_t len = walk_any(C, dirs, m, n, G, lds, rev, band_hi);
                 fence_wave_memory();
                 if (len < 0) {
                     plen = -2;
@@ -304,44 +359,96 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
 
 // ---- host side ----
 
-static int choose_cols(int32_t max_len) {
-    if (max_len > 768) return 8;
-    if (max_len > 256) return 4;
-    return 2;
+// Relative per-step cost of the 2-, 4- and 8-column sweeps.  Defaults:
+// instructions per step of the compiled loops (16-step groups, stores and
+// refills included).  nw_autotune replaces them, per device, with measured
+// times (tuning_table).
+constexpr int32_t kStepCostDirs[3] = {16, 27, 48};
+constexpr int32_t kStepCostScore[3] = {12, 18, 31};
+constexpr int kMaxDevices = 64;
+
+namespace {
+struct Tuning {
+    std::mutex mu;
+    bool tuned[kMaxDevices] = {};
+    int32_t cost[kMaxDevices][2][3] = {};  // [device][dirs][width]
+};
+Tuning& tuning() {
+    static Tuning t;
+    return t;
+}
+}  // namespace
+
+static void step_costs(int device, bool dirs, int32_t out[3]) {
+    Tuning& T = tuning();
+    std::lock_guard<std::mutex> lock(T.mu);
+    const bool have = device >= 0 && device < kMaxDevices && T.tuned[device];
+    for (int c = 0; c < 3; ++c)
+        out[c] = have ? T.cost[device][dirs][c] : (dirs ? kStepCostDirs[c] : kStepCostScore[c]);
 }
 
+void set_step_costs(int device, const int32_t dirs[3], const int32_t score[3]) {
+    if (device < 0 || device >= kMaxDevices) return;
+    Tuning& T = tuning();
+    std::lock_guard<std::mutex> lock(T.mu);
+    for (int c = 0; c < 3; ++c) {
+        T.cost[device][1][c] = dirs[c];
+        T.cost[device][0][c] = score[c];
+    }
+    T.tuned[device] = true;
+}
+
+void reset_step_costs() {
+    Tuning& T = tuning();
+    std::lock_guard<std::mutex> lock(T.mu);
+    for (bool& t : T.tuned) t = false;
+}
+
+// Cost weight that keeps a width from ever being picked (products stay far
+// below 2^63 for every admissible length).
+constexpr int32_t kExcluded = 1 << 20;
+constexpr int kMaxCols = 8;  // slots are sized for the widest sweep, which bounds the others
+
 struct Layout {
-    int C;
     int64_t nslots, grid;
     size_t off_order, off_bnd, off_dirs, off_rev, total;
     int64_t bnd_stride, dirs_stride, rev_stride;
 };
 
-// Per-call workspace for direction slots is capped: a persistent wave needs a
-// slot that holds the full grid of the largest pair, so very long pairs get
-// fewer waves.
-constexpr size_t kSlotBudget = size_t(48) << 30;
+// A persistent wave needs a private slot that holds the directions of the
+// largest pair's full grid (0.25 B per cell).  The workspace-size query asks
+// for one slot per resident wave, up to kSlotBudget of the device's HBM;
+// a launch uses as many slots as the workspace it is given holds (at least
+// one block's worth), so a smaller workspace only costs parallelism.
+constexpr size_t kSlotBudget = size_t(128) << 30;
+constexpr size_t kHeaderBytes = 1024;  // queue, hist[64], cursor[64]
 
-static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di, bool banded = false) {
+static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di,
+                         size_t ws_limit = SIZE_MAX) {
     Layout L{};
-    L.C = banded ? 2 : choose_cols(max_len);
-    const int64_t cols = (int64_t)kWave * L.C;
-    const int64_t want = ((int64_t)njobs + kWavesPerBlock - 1) / kWavesPerBlock;
-    int64_t cap = (int64_t)di.cus * kBlocksPerCu;
-    if (dirs) {
-        const int64_t ml = std::max<int32_t>(max_len, 1);
-        const int64_t slot = ((ml + cols - 1) / cols) * groups_for_rows((int)ml) * kWave * L.C * 4;
-        cap = std::max<int64_t>(1, std::min<int64_t>(cap, (int64_t)(kSlotBudget / (size_t)slot / kWavesPerBlock)));
-    }
-    L.grid = std::max<int64_t>(1, std::min(want, cap));
-    L.nslots = L.grid * kWavesPerBlock;
+    const int64_t cols = (int64_t)kWave * kMaxCols;
     const int64_t ml = std::max<int32_t>(max_len, 1);
     L.bnd_stride = (int64_t)align_up((size_t)(ml + 2), 64);
     const int64_t groups = groups_for_rows((int)ml);
     const int64_t nstrips = (ml + cols - 1) / cols;
-    L.dirs_stride = dirs ? (int64_t)align_up((size_t)(nstrips * groups * kWave * L.C), 64) : 0;
+    L.dirs_stride = dirs ? (int64_t)align_up((size_t)(nstrips * groups * cols), 64) : 0;
     L.rev_stride = dirs ? (int64_t)align_up((size_t)(2 * ml + 4), 256) : 0;
-    size_t off = 1024;  // header: queue, hist[64], cursor[64]
+    // bytes per block of slots (the three per-slot arrays are padded per array)
+    const size_t per_block = (size_t)kWavesPerBlock * ((size_t)L.bnd_stride * 4 + (size_t)L.dirs_stride * 4 +
+                                                       (size_t)L.rev_stride);
+    const size_t fixed = align_up(kHeaderBytes + (size_t)std::max(njobs, 1) * 4, 256) + 3 * 256;
+    const int64_t want = ((int64_t)njobs + kWavesPerBlock - 1) / kWavesPerBlock;
+    int64_t grid = std::min<int64_t>(std::max<int64_t>(want, 1), (int64_t)di.cus * kBlocksPerCu);
+    const size_t budget = std::min(ws_limit, fixed + std::max(kSlotBudget, per_block));
+    if (budget < fixed + per_block) {
+        L.total = fixed + per_block;  // too small: the caller gets NW_ENOSPC
+        L.grid = 0;
+        return L;
+    }
+    grid = std::max<int64_t>(1, std::min<int64_t>(grid, (int64_t)((budget - fixed) / per_block)));
+    L.grid = grid;
+    L.nslots = L.grid * kWavesPerBlock;
+    size_t off = kHeaderBytes;
     L.off_order = off;
     off = align_up(off + (size_t)std::max(njobs, 1) * 4, 256);
     L.off_bnd = off;
@@ -350,39 +457,27 @@ static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const Device
     off = align_up(off + (size_t)L.nslots * L.dirs_stride * 4, 256);
     L.off_rev = off;
     off = align_up(off + (size_t)L.nslots * L.rev_stride, 256);
-    L.total = off;
+    // report the size the slot count was derived from, so that a workspace of
+    // exactly this size yields the same grid again
+    L.total = std::max(off, fixed + (size_t)L.grid * per_block);
     return L;
 }
 
-size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di, bool banded) {
-    return layout_for(njobs, max_len, dirs, di, banded).total;
+size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di) {
+    return layout_for(njobs, max_len, dirs, di).total;
 }
 
-template <int C, bool DIRS, bool ALLPAIRS, bool BANDED>
+template <bool DIRS, bool ALLPAIRS, bool BANDED>
 static void launch_engine(const KArgs& A, int64_t grid, hipStream_t st) {
     ProfScope ps(BANDED ? (DIRS ? "nw_batch_banded" : "nw_batch_banded_score")
                         : (ALLPAIRS ? "nw_allpairs" : (DIRS ? "nw_batch" : "nw_batch_score")),
                  st);
-    hipLaunchKernelGGL((k_batch<C, DIRS, ALLPAIRS, BANDED>), dim3((unsigned)grid), dim3(kBlockThreads), 0,
-                       st, A);
-}
-
-template <bool ALLPAIRS, bool BANDED>
-static void launch_c(int C, bool dirs, const KArgs& A, int64_t grid, hipStream_t st) {
-    if (dirs) {
-        if (C == 8) launch_engine<8, true, ALLPAIRS, BANDED>(A, grid, st);
-        else if (C == 4) launch_engine<4, true, ALLPAIRS, BANDED>(A, grid, st);
-        else launch_engine<2, true, ALLPAIRS, BANDED>(A, grid, st);
-    } else {
-        if (C == 8) launch_engine<8, false, ALLPAIRS, BANDED>(A, grid, st);
-        else if (C == 4) launch_engine<4, false, ALLPAIRS, BANDED>(A, grid, st);
-        else launch_engine<2, false, ALLPAIRS, BANDED>(A, grid, st);
-    }
+    hipLaunchKernelGGL((k_batch<DIRS, ALLPAIRS, BANDED>), dim3((unsigned)grid), dim3(kBlockThreads), 0, st, A);
 }
 
 int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st, const DeviceInfo& di) {
-    const Layout L = layout_for(job.njobs, job.max_len, job.dirs, di, job.banded);
-    if (ws_bytes < L.total) return NW_ENOSPC;
+    const Layout L = layout_for(job.njobs, job.max_len, job.dirs, di, ws_bytes);
+    if (L.grid == 0 || ws_bytes < L.total) return NW_ENOSPC;
     if (job.njobs == 0) return NW_OK;
     uint8_t* base = (uint8_t*)ws;
     const Consts K = job.dirs ? dirs_consts(job.sc) : score_consts(job.sc);
@@ -398,6 +493,10 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.kdm = K.kdm;
     A.kdx = K.kdx;
     A.gap = job.sc.gap;
+    step_costs(di.device, job.dirs, A.step_cost);
+    if (job.force_cols) {
+        for (int c = 0; c < 3; ++c) A.step_cost[c] = ((2 << c) == job.force_cols) ? 1 : kExcluded;
+    }
     A.scores = job.scores;
     A.paths = job.paths;
     A.path_off = job.path_off;
@@ -429,13 +528,18 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
         hipLaunchKernelGGL(k_hist<true>, dim3(pb), dim3(256), 0, st, A);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor);
         hipLaunchKernelGGL(k_scatter<true>, dim3(pb), dim3(256), 0, st, A);
-        launch_c<true, false>(L.C, job.dirs, A, L.grid, st);
+        launch_engine<false, true, false>(A, L.grid, st);
     } else {
         hipLaunchKernelGGL(k_hist<false>, dim3(pb), dim3(256), 0, st, A);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor);
         hipLaunchKernelGGL(k_scatter<false>, dim3(pb), dim3(256), 0, st, A);
-        if (job.banded) launch_c<false, true>(L.C, job.dirs, A, L.grid, st);
-        else launch_c<false, false>(L.C, job.dirs, A, L.grid, st);
+        if (job.banded) {
+            if (job.dirs) launch_engine<true, false, true>(A, L.grid, st);
+            else launch_engine<false, false, true>(A, L.grid, st);
+        } else {
+            if (job.dirs) launch_engine<true, false, false>(A, L.grid, st);
+            else launch_engine<false, false, false>(A, L.grid, st);
+        }
     }
     return hipGetLastError() == hipSuccess ? NW_OK : NW_EDEVICE;
 }

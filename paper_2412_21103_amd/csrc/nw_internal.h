@@ -67,6 +67,9 @@ struct BatchJob {
     int32_t* w_used;
     uint8_t* status;
     int64_t* cells;
+    // 0: sweep width per pass from the cost table; 2, 4 or 8: that width
+    // always (used by the autotuner)
+    int force_cols;
 };
 
 // Cooperative single-pair engine (nw_single.hip): used for one pair with at
@@ -77,10 +80,16 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
                 bool dirs, int32_t* score, uint8_t* path, int64_t* path_len, void* ws,
                 size_t ws_bytes, hipStream_t stream, const DeviceInfo& di);
 
-size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di,
-                             bool banded = false);
+// Workspace for full occupancy (one slot per resident wave, within the
+// library's HBM budget); launch_batch runs with fewer waves when given less,
+// down to one block of slots.
+size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di);
 int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t stream,
                  const DeviceInfo& di);
+
+// Sweep-width cost table (per device), filled by nw_autotune.
+void set_step_costs(int device, const int32_t dirs[3], const int32_t score[3]);
+void reset_step_costs();
 
 // Band model (nw_mlp.hip).
 int launch_features(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,

@@ -62,6 +62,12 @@ def test_host_argument_checks():
                             vp(1), vp(0), vp(1), vp(1), vp(1), 1, vp(0)) == nwp.NW_EINVAL
     assert L.nw_align_batch(0, vp(0), vp(0), vp(0), vp(0), vp(0), 10, nwp.Scoring(1, -1, -1), 0,
                             vp(0), vp(0), vp(0), vp(0), vp(0), 0, vp(0)) == nwp.NW_OK
+    # graph replay needs a real stream; unknown flag bits are rejected
+    assert L.nw_align_batch(4, vp(1), vp(1), vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), nwp.GRAPH,
+                            vp(1), vp(1), vp(1), vp(1), vp(1), 1 << 30, vp(0)) == nwp.NW_EINVAL
+    assert L.nw_align_batch(4, vp(1), vp(1), vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), 0x4,
+                            vp(1), vp(1), vp(1), vp(1), vp(1), 1 << 30, vp(1)) == nwp.NW_EINVAL
+    L.nw_release_caches()
     assert L.nw_allpairs_scores(-3, vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), vp(1), vp(1), 1,
                                 vp(0)) == nwp.NW_EINVAL
     assert L.nw_allpairs_scores(70000, vp(1), vp(1), vp(1), 10, nwp.Scoring(1, -1, -1), vp(1), vp(1),

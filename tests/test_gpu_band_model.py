@@ -1,0 +1,80 @@
+"""What the trained band model gains over the method without it.
+
+The model is trained on the GPU (labels from the full-DP method, features,
+forward/backward/Adam kernels) on pairs from the learned-band workload
+distribution, then evaluated on pairs from disjoint seeds against (a) the
+certified band doubling from w = 0 and (b) the full grid.  All three return
+identical scores and paths (and a sample matches the oracle); the model must
+cut the cells swept and certify most pairs on the first banded pass."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import config_band_batch, pack_pairs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2412_21103_amd as nwp  # noqa: E402
+from paper_2412_21103_amd import band_model  # noqa: E402
+from gpu_util import say  # noqa: E402
+
+
+def _dev(x, dt):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to("cuda")
+
+
+def _to_dev(pairs):
+    pool, ao, al, bo, bl = pack_pairs(pairs)
+    return (_dev(pool, np.uint8), _dev(ao, np.int64), _dev(al, np.int32), _dev(bo, np.int64),
+            _dev(bl, np.int32), int(max(al.max(), bl.max())))
+
+
+def _paths(out, n):
+    s, paths, poff, plen = (t.cpu().numpy() for t in out[:4])
+    return s, [paths[poff[k]:poff[k] + plen[k]] for k in range(n)]
+
+
+def test_trained_model_gain():
+    say("band model: generating train (seed 5100) and test (seed 5200) pairs")
+    train = config_band_batch(seed=5100, npairs=2048)
+    test = config_band_batch(seed=5200, npairs=512)
+    dtr, dte = _to_dev(train), _to_dev(test)
+    x, _, wc, target = band_model.features_and_labels(*dtr)
+    say("band model: training")
+    mlp, hist = band_model.train(x, target, epochs=150, batch=256, lr=3e-3, tau=0.9, seed=1)
+    assert hist[-1] < 0.05 * hist[0], hist[::25]
+
+    say("band model: full grid, doubling from 0, learned")
+    full = nwp.align_batch(*dte)
+    s_full, p_full = _paths(full, len(test))
+    dbl = nwp.align_batch_banded(*dte, w_default=0)
+    lrn = nwp.align_batch_learned(*dte, mlp, 0.1)
+    torch.cuda.synchronize()
+    for tag, out in (("doubling", dbl), ("learned", lrn)):
+        s, p = _paths(out, len(test))
+        assert (s == s_full).all(), tag
+        for k in range(len(test)):
+            assert p[k].tolist() == p_full[k].tolist(), (tag, k)
+
+    full_cells = float(sum(len(a) * len(b) for a, b in zip(test.a, test.b)))
+    c_dbl = float(dbl[6].sum()) / full_cells
+    c_lrn = float(lrn[6].sum()) / full_cells
+    first = float((lrn[5].cpu().numpy() & 1).mean())
+    say(f"band model: cells swept / full grid: doubling {c_dbl:.3f}, learned {c_lrn:.3f}; "
+        f"learned first-pass certified {first:.3f}")
+    assert c_lrn < 0.7 * c_dbl
+    assert c_lrn < 0.6
+    assert first > 0.7
+
+    # a sample of pairs against the oracle (two of them among the largest)
+    rng = np.random.default_rng(0)
+    cost = np.array([len(a) * len(b) for a, b in zip(test.a, test.b)])
+    sample = list(rng.choice(np.nonzero(cost < 3e7)[0], 4, replace=False)) + list(np.argsort(cost)[-2:])
+    say(f"band model: oracle on pairs {sample}")
+    for k in sample:
+        s_ref, p_ref = oracle.align(test.a[k], test.b[k], oracle.PAPER_SCORING)
+        assert s_full[k] == s_ref and p_full[k].tolist() == p_ref.tolist(), k

@@ -79,6 +79,35 @@ def test_batch_matches_oracle():
     assert (s2 == s_ref).all()
 
 
+def test_batch_with_smaller_workspace():
+    # a workspace below the full-occupancy size runs fewer waves, same results;
+    # one below a single block of slots is rejected before any launch
+    import paper_2412_21103_amd as nwp
+    pairs = config_batch(seed=33, npairs=200, lo=1, hi=900)
+    pool, ao, al, bo, bl = pack_pairs(pairs)
+    max_len = int(max(al.max(), bl.max()))
+    full = nwp.batch_workspace_size(len(pairs), max_len)
+    t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to("cuda")
+    args = [t(pool, np.uint8), t(ao, np.int64), t(al, np.int32), t(bo, np.int64), t(bl, np.int32)]
+    s_ref, p_ref = oracle.align_batch(pool, ao, al, bo, bl, P)
+    for frac in (4, 37):
+        say(f"batch workspace 1/{frac}")
+        ws = torch.empty(full // frac, dtype=torch.uint8, device="cuda")
+        s, paths, poff, plen = nwp.align_batch(*args, max_len, P, workspace=ws)
+        torch.cuda.synchronize()
+        s, paths, poff, plen = (x.cpu().numpy() for x in (s, paths, poff, plen))
+        assert (s == s_ref).all()
+        for k in range(len(pairs)):
+            assert paths[poff[k]:poff[k] + plen[k]].tolist() == p_ref[k].tolist(), (frac, k)
+    tiny = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    out = torch.empty(len(pairs), dtype=torch.int32, device="cuda")
+    st = nwp.lib().nw_align_batch(len(pairs), nwp._ptr(args[0]), nwp._ptr(args[1]), nwp._ptr(args[2]),
+                                  nwp._ptr(args[3]), nwp._ptr(args[4]), max_len, nwp.Scoring(*P),
+                                  nwp.SCORE_ONLY, nwp._ptr(out), None, None, None, nwp._ptr(tiny),
+                                  tiny.numel(), None)
+    assert st == nwp.NW_ENOSPC
+
+
 def test_batch_pair_beyond_max_len_is_flagged():
     rng = np.random.default_rng(32)
     A = [random_seq(rng, 50), random_seq(rng, 120), random_seq(rng, 30)]
