@@ -300,11 +300,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-band", action="store_true", help="skip the learned-band batch")
     ap.add_argument("--band-pairs", type=int, default=8192)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="first run a plain device copy of BYTES bytes (int32 elementwise), the reference "
+                         "kernel that scales the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(pairs are independent, see DESIGN.md for how the work would shard)", file=sys.stderr)
         return 2
+    if args.copy_probe > 0:
+        import torch
+        src = torch.ones(args.copy_probe // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.mul(src, 1, out=dst)
+        torch.cuda.synchronize()
+        print(f"bench: copy probe of {args.copy_probe} bytes done", file=sys.stderr, flush=True)
+        del src, dst
     if args.workload == "batch":
         print(json.dumps(bench_batch(args)), flush=True)
         return 0
