@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <initializer_list>
@@ -412,8 +413,10 @@ int nw_autotune(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const
             }
             per_unit[c] = units > 0 ? (double)best / units : 1.0;
         }
-        for (int c = 0; c < 3; ++c)
-            table[dirs][c] = (int32_t)std::max(1.0, std::min(1e5, 1000.0 * per_unit[c] / per_unit[2]));
+        for (int c = 0; c < 3; ++c) {
+            const double rel = (c == 2) ? 1.0 : per_unit[c] / per_unit[2];
+            table[dirs][c] = (int32_t)std::lround(std::max(1.0, std::min(1e5, 1000.0 * rel)));
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -163,7 +163,7 @@ constexpr int32_t kNegW = -(1 << 29);      // -infinity in the W domain
 template <int C, bool DIRS>
 __device__ __forceinline__ int32_t fill_pair(const KArgs& A, const uint8_t* pa, const uint8_t* pb,
                                              int m, int n, bool full, int w, int32_t* bnd,
-                                             uint32_t* dirs, uint32_t* lds, int* G_out,
+                                             int32_t* spare, uint32_t* dirs, uint32_t* lds, int* G_out,
                                              int64_t* cells) {
     constexpr int kCols = kWave * C;
     const int32_t vinit = DIRS ? 1 : 0;
@@ -182,7 +182,7 @@ __device__ __forceinline__ int32_t fill_pair(const KArgs& A, const uint8_t* pa, 
         const int re = full ? m : min(m, j0 + kCols - lo_d + w);
         const int r0 = rs - 1, rows = re - rs + 1;
         const int ksel = (n - 1 - j0) % C;
-        PlainIO io{s == 0 ? nullptr : bnd, s == nstrips - 1 ? nullptr : bnd, rows, vinit};
+        PlainIO io{s == 0 ? nullptr : bnd, s == nstrips - 1 ? nullptr : bnd, spare, rows, vinit};
         io.r0 = r0;
         io.in_hi = (s == 0) ? m : prev_hi;
         io.beyond = full ? 0 : vneg;
@@ -229,11 +229,11 @@ __device__ __forceinline__ int pick_cols(const KArgs& A, int m, int n, bool full
 
 template <bool DIRS>
 __device__ __forceinline__ int32_t fill_any(int C, const KArgs& A, const uint8_t* pa, const uint8_t* pb, int m,
-                                            int n, bool full, int w, int32_t* bnd, uint32_t* dirs,
+                                            int n, bool full, int w, int32_t* bnd, int32_t* spare, uint32_t* dirs,
                                             uint32_t* lds, int* G, int64_t* cells) {
-    if (C == 8) return fill_pair<8, DIRS>(A, pa, pb, m, n, full, w, bnd, dirs, lds, G, cells);
-    if (C == 4) return fill_pair<4, DIRS>(A, pa, pb, m, n, full, w, bnd, dirs, lds, G, cells);
-    return fill_pair<2, DIRS>(A, pa, pb, m, n, full, w, bnd, dirs, lds, G, cells);
+    if (C == 8) return fill_pair<8, DIRS>(A, pa, pb, m, n, full, w, bnd, spare, dirs, lds, G, cells);
+    if (C == 4) return fill_pair<4, DIRS>(A, pa, pb, m, n, full, w, bnd, spare, dirs, lds, G, cells);
+    return fill_pair<2, DIRS>(A, pa, pb, m, n, full, w, bnd, spare, dirs, lds, G, cells);
 }
 
 __device__ __forceinline__ int64_t walk_any(int C, const uint32_t* dirs, int m, int n, int G, uint32_t* lds,
@@ -251,6 +251,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
     uint32_t* lds = smem[wave];
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     int32_t* bnd = A.bnd + slot * A.bnd_stride;
+    int32_t* spare = bnd + A.bnd_stride - 1;  // past every grid row (stride >= max_len + 2)
     uint32_t* dirs = DIRS ? A.dirs + slot * A.dirs_stride : nullptr;
     uint8_t* rev = DIRS ? A.rev + slot * A.rev_stride : nullptr;
 
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
                     full = !A.band_ok || w >= mn ||
                            (int64_t)(2 * kWave + dlt + 2 * (int64_t)w) * 1024 >= (int64_t)A.frac_1024 * m;
                     C = uniform(pick_cols(A, m, n, full, w));
-                    const int32_t v = fill_any<DIRS>(C, A, P.a, P.b, m, n, full, w, bnd, dirs, lds, &G, &cells);
+                    const int32_t v = fill_any<DIRS>(C, A, P.a, P.b, m, n, full, w, bnd, spare, dirs, lds, &G, &cells);
                     ++passes;
                     score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
                     if (full) break;
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
                 cells_out = cells;
             } else {
                 C = uniform(pick_cols(A, m, n, true, 0));
-                const int32_t v = fill_any<DIRS>(C, A, P.a, P.b, m, n, true, 0, bnd, dirs, lds, &G, &cells);
+                const int32_t v = fill_any<DIRS>(C, A, P.a, P.b, m, n, true, 0, bnd, spare, dirs, lds, &G, &cells);
                 score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
             }
             if constexpr (DIRS && !ALLPAIRS) {

@@ -6,9 +6,10 @@
 // strip to its left, whose owner took an earlier ticket and is therefore
 // already running or done: the schedule cannot deadlock, and the grid never
 // needs more blocks than fit on the device.  A strip's right boundary column
-// goes to the next strip through 64-bit {value, epoch} slots (TaggedIO), so
-// the fill runs as one anti-diagonal front across all strips, each strip a
-// fixed lag behind its left neighbour.
+// goes to the next strip through a ring in LDS when both strips belong to
+// one block and through 64-bit {value, epoch} slots in HBM otherwise
+// (CoopIO), so the fill runs as one anti-diagonal front across all strips,
+// each strip a fixed lag behind its left neighbour.
 //
 // Traceback.  A single serial walk from (m, n) would take one dependent
 // lookup per move (about 130k moves for a 65,536-base pair).  Instead every
@@ -54,6 +55,41 @@ struct CoopArgs {
     int32_t* score;
 };
 
+// Dynamic LDS of a block: the waves' row tables, then one boundary ring per
+// wave (the ring wave w reads, written by wave w-1), a spare slot, and the
+// rings' consumed-row counters.
+template <int C>
+struct CoopLds {
+    static constexpr int kTableWords = kCoopWaves * StripShape<C>::kLdsWords;
+    static constexpr int kTableWordsAligned = (kTableWords + 1) & ~1;
+    static constexpr int kRingWords = 2 * kRing;
+    static constexpr int kSpareWord = kTableWordsAligned + kCoopWaves * kRingWords;
+    static constexpr int kCountWord = kSpareWord + 2;
+    static constexpr int kWords = kCountWord + kCoopWaves;
+};
+
+template <int C, bool DIRS, int IN, int OUT>
+__device__ __forceinline__ int32_t coop_sweep(const CoopArgs& A, int s, int wave, uint32_t* lds, uint32_t* dyn,
+                                              int j0, int ksel) {
+    lds_u64* rings = (lds_u64*)(dyn + CoopLds<C>::kTableWordsAligned);
+    lds_i32* consumed = (lds_i32*)(dyn + CoopLds<C>::kCountWord);
+    uint64_t* col = A.bnd + (int64_t)s * A.bnd_stride;
+    const CoopIO<IN, OUT, DIRS> io{s > 0 ? col - A.bnd_stride : nullptr,
+                                   col,
+                                   col + A.bnd_stride - 1,
+                                   rings + wave * kRing,
+                                   rings + ((wave + 1) % kCoopWaves) * kRing,
+                                   (lds_u64*)(dyn + CoopLds<C>::kSpareWord),
+                                   consumed + wave,
+                                   consumed + (wave + 1) % kCoopWaves,
+                                   A.m,
+                                   A.vinit,
+                                   A.epoch,
+                                   A.err};
+    return sweep_strip<C, DIRS>(A.a, A.m, A.b, A.n, j0, A.kdm, A.kdx, A.vinit, A.vinit, io,
+                                DIRS ? A.dirs + (size_t)s * A.G * kWave * C : nullptr, lds, ksel);
+}
+
 template <int C, bool DIRS>
 __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
     extern __shared__ uint32_t dyn[];
@@ -65,25 +101,34 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
         if (threadIdx.x == 0) ticket_s = atomicAdd(A.ticket, 1);
         __syncthreads();
         const int k = uniform(ticket_s);
+        // every wave is done with the previous group's rings: clear them and
+        // their counters (row tags start at 1, so a zero slot is never ready)
+        for (int q = CoopLds<C>::kTableWordsAligned + threadIdx.x; q < CoopLds<C>::kWords; q += kCoopThreads)
+            ((__attribute__((address_space(3))) uint32_t*)dyn)[q] = 0;
         __syncthreads();
         if (k >= A.ngroups) break;
         const int s = k * kCoopWaves + wave;
         if (s < A.nstrips) {
             const int j0 = s * kCols;
             const int ksel = (A.n - 1 - j0) % C;
-            const TaggedIO io{s == 0 ? nullptr : A.bnd + (int64_t)(s - 1) * A.bnd_stride,
-                              s == A.nstrips - 1 ? nullptr : A.bnd + (int64_t)s * A.bnd_stride,
-                              A.m,
-                              A.vinit,
-                              A.epoch,
-                              A.err,
-                              wave > 0,
-                              wave < kCoopWaves - 1};
-            const int32_t v = sweep_strip<C, DIRS>(A.a, A.m, A.b, A.n, j0, A.kdm, A.kdx, A.vinit,
-                                                   A.vinit, io,
-                                                   DIRS ? A.dirs + (size_t)s * A.G * kWave * C : nullptr,
-                                                   lds, ksel);
-            if (s == A.nstrips - 1) {
+            const bool last = (s == A.nstrips - 1);
+            int32_t v;
+            // input: none (first strip), the block's previous wave (LDS), or the
+            // previous block's last wave (HBM); output likewise
+            if (s == 0) {
+                v = last ? coop_sweep<C, DIRS, kIoNone, kIoNone>(A, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoNone, kIoLds>(A, s, wave, lds, dyn, j0, ksel);
+            } else if (wave == 0) {
+                v = last ? coop_sweep<C, DIRS, kIoGlobal, kIoNone>(A, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoGlobal, kIoLds>(A, s, wave, lds, dyn, j0, ksel);
+            } else if (wave < kCoopWaves - 1) {
+                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoLds, kIoLds>(A, s, wave, lds, dyn, j0, ksel);
+            } else {
+                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoLds, kIoGlobal>(A, s, wave, lds, dyn, j0, ksel);
+            }
+            if (last) {
                 const int lsel = (A.n - 1 - j0) / C;
                 const int32_t vv = __builtin_amdgcn_readlane(v, lsel);
                 A.score[0] = (DIRS ? ((vv - 1) >> 2) : vv) + A.gap * (A.m + A.n);
@@ -382,7 +427,8 @@ __global__ void k_zero_small(int32_t* p, int n) {
 
 // ---- host side ----
 
-constexpr int kCoopC = 1;
+constexpr int kCoopC = 2;  // 128-column strips: half the hops of 64-column ones at a 1.3x step cost
+static_assert(CoopLds<kCoopC>::kWords * 4 <= kCoopDynLds, "cooperative fill LDS");
 
 struct CoopLayout {
     int nstrips, ngroups, G;
@@ -398,13 +444,13 @@ static CoopLayout coop_layout(int64_t m, int64_t n, bool dirs) {
     L.nstrips = (int)((n + cols - 1) / cols);
     L.ngroups = (L.nstrips + kCoopWaves - 1) / kCoopWaves;
     L.G = groups_for_rows((int)m);
-    L.bnd_stride = (int64_t)align_up((size_t)(m + 1), 32);
+    L.bnd_stride = (int64_t)align_up((size_t)(m + 2), 32);  // rows 0..m and a spare slot
     L.seg_stride = (int64_t)align_up((size_t)(m + cols + 16), 64);
     L.info_stride = kInfoHead + 3 * cols;
     const size_t ns = (size_t)L.nstrips;
     size_t off = 256;
     L.off_bnd = off;
-    off = align_up(off + (size_t)std::max(L.nstrips - 1, 0) * L.bnd_stride * 8, 256);
+    off = align_up(off + (size_t)L.nstrips * L.bnd_stride * 8, 256);  // one column per strip
     L.off_dirs = off;
     if (dirs) {
         off = align_up(off + ns * L.G * kWave * kCoopC * 4, 256);

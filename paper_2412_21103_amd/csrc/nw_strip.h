@@ -10,61 +10,69 @@
 // DPP wave shift.  Lane 0 takes that value from a queue register R: R is
 // shifted left one lane per step, so lane 0 consumes the next row's
 // left-boundary value while lane 63 appends its own last-column value, which
-// is the strip's right boundary for the next strip.  Every 16 steps lanes
-// 48..63 (the last 16 outputs) are written out and lanes 0..15 are refilled
-// with the next 16 inputs; whatever sits in lanes 16..47 reaches lane 0 only
-// after the next refill has overwritten it, so inputs are needed just one
-// group (16 rows) ahead.
+// is the strip's right boundary for the next strip.  The sweep runs in groups
+// of kGroup = 32 steps: at a group's end lanes 32..63 (the last 32 outputs)
+// are written out and lanes 0..31 are refilled with the next 32 inputs, so
+// inputs are needed just one group ahead.  Group-end bookkeeping (refill,
+// output, table upkeep, stores) is paid once per 32 steps.
 //
 // Boundary columns travel through an IO policy: PlainIO for a wave that
-// sweeps all strips of a pair itself, TaggedIO when neighbouring strips run
-// on different waves (see the cooperative kernel).
+// sweeps all strips of a pair itself, CoopIO when neighbouring strips run on
+// different waves (see the cooperative kernel).
 //
-// The substitution term comes from a per-row table in LDS: for row i the word
-// holds four signed bytes, byte y = term(a_i == y).  Lane (l, k) reads byte
+// The substitution term comes from a per-row table in LDS (a circular buffer,
+// see kTabRows): for row i the word holds four signed bytes, byte y =
+// term(a_i == y).  Lane (l, k) reads byte
 // b_j of the row it is on with one ds_read_i8.  Rows outside 1..m hold -128,
 // which freezes the lanes that are above or below the matrix (see
 // nw_common.h), so the sweep needs no per-lane predicates.
 //
 // Directions: each lane shifts the 2-bit tag of every cell of column k into a
-// 32-bit accumulator; after 16 steps lane l stores its C words contiguously,
-// giving the layout  dirs[strip][group g][lane l][column k]  (one word per
-// 16 consecutive steps of one column).  Step t of lane l is row t - l + 1, so
-// cell (i, j) lives in word (g = (i-1+l) / 16) at bits 2*((i-1+l) % 16).
+// 32-bit accumulator, one per 16 steps (two per group); lane l stores its C
+// words of each half contiguously, giving the layout
+//   dirs[strip][16-step group g][lane l][column k]
+// (one word per 16 consecutive steps of one column).  Step t of lane l is
+// row t - l + 1, so cell (i, j) lives in word (g = (i-1+l) / 16) at bits
+// 2*((i-1+l) % 16).
 #pragma once
 
 #include "nw_common.h"
 
 namespace nw {
 
-constexpr int kWinRows = 192;   // rows per table window
-constexpr int kWinGroups = 8;   // 16-step groups served by one window
+constexpr int kGroup = 32;  // steps per group
+
+// Row table: a circular LDS buffer of kTabRows row words (row i at index
+// i & (kTabRows - 1)) followed by a copy of its first kGroup words, so the
+// kGroup rows one lane reads in a group are always contiguous and the
+// per-step offsets fold into the ds_read immediates.  Rows outside 1..m hold
+// the sentinel word.  Word kTabSpare takes the writes of lanes with nothing
+// to write.
+constexpr int kTabRows = 256;
+constexpr int kTabSpare = kTabRows + kGroup;
+constexpr int kTabWords = kTabSpare + 1;
 
 template <int C>
 struct StripShape {
     static constexpr int kCols = kWave * C;
-    // LDS words per wave: two table windows, or the traceback window
-    static constexpr int kLdsWords = (2 * kWinRows > 64 * C) ? 2 * kWinRows : 64 * C;
+    // LDS words per wave: the row table, or the traceback window
+    static constexpr int kLdsWords = (kTabWords > 64 * C) ? kTabWords : 64 * C;
 };
 
-// Lane 63 finishes row m at step m + 62, and its value enters the queue at the
-// start of step m + 63, which must lie in a group that the loop runs (the
-// group's end flushes it).  So the sweep runs floor((m + 63) / 16) + 1 groups.
-__host__ __device__ __forceinline__ int groups_for_rows(int m) { return (m + 79) >> 4; }
-__host__ __device__ __forceinline__ int steps_for_rows(int m) { return groups_for_rows(m) << 4; }
+// Lane 63 finishes row m at step m + 62, and its value enters the queue in
+// step m + 63, which must lie in a group that the loop runs (the group's end
+// flushes it).  So the sweep runs floor((m + 63) / 32) + 1 groups, and stores
+// twice as many 16-step direction words per column.
+__host__ __device__ __forceinline__ int sweep_groups(int m) { return (m + 95) >> 5; }
+__host__ __device__ __forceinline__ int groups_for_rows(int m) { return 2 * sweep_groups(m); }  // 16-step units
 
-// Fill one table window: word p <-> row wlo + p.
-__device__ __forceinline__ void write_window(uint32_t* win, const uint8_t* a, int m, int wlo,
-                                             int kdm, int kdx, int lane) {
-#pragma unroll
-    for (int e = 0; e < kWinRows / kWave; ++e) {
-        int p = lane + kWave * e;
-        int r = wlo + p;
-        uint32_t w = kSentinelWord;
-        if (r >= 1 && r <= m) w = row_word(a[r - 1], kdm, kdx);
-        win[p] = w;
-    }
-}
+// Group-end memory traffic is issued by every lane without a branch: lanes
+// with nothing to load or store use a spare slot.  Vector memory operations
+// of a wave retire in order and stores count in the same counter as loads,
+// so with a branch around a store the compiler cannot tell how many
+// operations follow a load and waits for all of them (vmcnt(0)); branch-free
+// issue lets it wait for exactly the load a refill needs, and the previous
+// group's stores stay in flight behind the steps.
 
 // Boundary IO for a wave that owns every strip of its pair: the previous
 // strip's right column sits in the wave's own scratch (bin, indexed by grid
@@ -73,18 +81,23 @@ __device__ __forceinline__ void write_window(uint32_t* win, const uint8_t* a, in
 // (a band); its rows are numbered locally from 1.  Inputs for grid rows above
 // in_hi, or beyond the sweep, lie outside the previous strip's region and
 // read `beyond`, a value that never wins (0, or the -infinity sentinel of a
-// band).  A missing bin means the grid's first column (vinit).
+// band).  A missing bin means the grid's first column (vinit).  `spare` is a
+// scratch slot nobody reads.
 struct PlainIO {
     const int32_t* bin;
     int32_t* bout;
+    int32_t* spare;
     int m;
     int32_t vinit;
     int r0 = 0;
     int in_hi = 1 << 30;
     int32_t beyond = 0;
     using Slot = int32_t;
+    static constexpr int kPrefetch = 2;  // groups a refill is loaded ahead (0: read at the group end)
     __device__ __forceinline__ Slot load(int r, bool want) const {
-        return (want && bin && r <= m && r0 + r <= in_hi) ? bin[r0 + r] : 0;
+        const bool ok = want && bin != nullptr && r <= m && r0 + r <= in_hi;
+        const int32_t* src = ok ? bin + r0 + r : spare;
+        return *src;
     }
     __device__ __forceinline__ int32_t value(Slot x, int r) const {
         if (r > m) return beyond;
@@ -93,46 +106,96 @@ struct PlainIO {
     }
     __device__ __forceinline__ bool ready(Slot, int, bool) const { return true; }
     __device__ __forceinline__ void store(int r, int32_t v, bool want) const {
-        if (bout && want) bout[r0 + r] = v;
+        int32_t* dst = (want && bout != nullptr) ? bout + r0 + r : spare;
+        *dst = v;
     }
     __device__ __forceinline__ void fail() const {}
     __device__ __forceinline__ bool failed() const { return false; }
+    __device__ __forceinline__ int room_probe() const { return 0; }
+    __device__ __forceinline__ void wait_room(int, int&) const {}
+    __device__ __forceinline__ void mark_consumed(int) const {}
 };
 
-// Boundary IO between strips swept by different waves, possibly on different
-// CUs or XCDs.  Each row slot is 64 bits, {value, epoch}, written with one
-// device-coherent atomic store; the reader polls the slot until it carries the
-// current call's epoch, so no separate flag (and no cache write-back) is
-// needed.  Polling gives up after a bounded number of rounds and raises *err.
-struct TaggedIO {
-    const uint64_t* bin;
-    uint64_t* bout;
+// Polling rounds before a boundary wait gives up and raises the failure flag:
+// a watchdog far beyond any legitimate wait (the last strip of a long pair
+// waits for the whole pipeline to reach it, milliseconds for 65,536 columns),
+// about 0.4 s of LDS polls or a few seconds of L2 polls.
+constexpr int kSpinLimit = 1 << 22;
+
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+typedef __attribute__((address_space(3))) int32_t lds_i32;
+
+constexpr int kRing = 1024;  // rows per LDS boundary ring
+
+// Boundary IO of the cooperative fill, typed by where the strip's input and
+// output column live (so each wave's code waits only on the counter its
+// input uses):
+//   kIoNone   - no neighbour (first strip: the grid's first column; last
+//               strip: no output);
+//   kIoLds    - the neighbour is another wave of the same block: a ring of
+//               kRing 64-bit {value, row} slots in LDS.  The reader polls until
+//               the slot carries the row it wants and publishes the last row it
+//               has read after each refill; the writer overwrites a slot only
+//               once the row kRing below has been read;
+//   kIoGlobal - the neighbour is in another block, possibly on another XCD:
+//               64-bit {value, epoch} slots in HBM written with device-scope
+//               stores; the reader polls until a slot carries the call's epoch.
+// With KEEP, ring output is also stored plainly to the global column, which
+// the traceback reads after the fill.
+enum { kIoNone = 0, kIoLds = 1, kIoGlobal = 2 };
+
+template <int IN, int OUT, bool KEEP>
+struct CoopIO {
+    const uint64_t* bin;  // global input column (kIoGlobal)
+    uint64_t* bout;       // global output column (kIoGlobal, or KEEP)
+    uint64_t* gspare;     // global slot nobody reads
+    lds_u64* lin;         // LDS input ring (kIoLds)
+    lds_u64* lout;        // LDS output ring (kIoLds)
+    lds_u64* lspare;      // LDS slot nobody reads
+    lds_i32* cin;         // last row read from the input ring (published here)
+    lds_i32* cout;        // last row the output ring's reader has read
     int m;
     int32_t vinit;
     uint32_t epoch;
     int32_t* err;
-    bool in_local;   // the left neighbour runs on the same CU (same block)
-    bool out_local;  // the right neighbour runs on the same CU
     using Slot = uint64_t;
-    // Waves of one block share the CU's L1, so block-local neighbours use
-    // workgroup-scope accesses (plain, L1-coherent); other neighbours may sit
-    // on another XCD and use device-scope (sc1) accesses.
+    // a global refill is loaded one group (32 steps, about one L2 round trip)
+    // ahead; a deeper prefetch would only add lag to the hop
+    static constexpr int kPrefetch = (IN == kIoGlobal) ? 1 : 0;
     __device__ __forceinline__ Slot load(int r, bool want) const {
-        if (!(want && bin && r <= m)) return 0;
-        return in_local ? __hip_atomic_load(bin + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                        : __hip_atomic_load(bin + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool ok = want && r <= m;
+        if constexpr (IN == kIoLds) {
+            lds_u64* p = ok ? lin + (r & (kRing - 1)) : lspare;
+            return *(volatile lds_u64*)p;
+        } else if constexpr (IN == kIoGlobal) {
+            const uint64_t* p = ok ? bin + r : gspare;
+            return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            return 0;
+        }
     }
     __device__ __forceinline__ int32_t value(Slot x, int r) const {
-        return r > m ? 0 : (bin ? (int32_t)(uint32_t)x : vinit);
+        if (r > m) return 0;
+        return IN == kIoNone ? vinit : (int32_t)(uint32_t)x;
     }
     __device__ __forceinline__ bool ready(Slot x, int r, bool want) const {
-        return !(want && bin && r <= m) || (uint32_t)(x >> 32) == epoch;
+        if constexpr (IN == kIoNone) return true;
+        const uint32_t tag = (IN == kIoLds) ? (uint32_t)r : epoch;
+        return !(want && r <= m) || (uint32_t)(x >> 32) == tag;
     }
     __device__ __forceinline__ void store(int r, int32_t v, bool want) const {
-        if (!(bout && want)) return;
-        const uint64_t x = ((uint64_t)epoch << 32) | (uint32_t)v;
-        if (out_local) __hip_atomic_store(bout + r, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        else __hip_atomic_store(bout + r, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if constexpr (OUT == kIoLds) {
+            lds_u64* p = want ? lout + (r & (kRing - 1)) : lspare;
+            *(volatile lds_u64*)p = ((uint64_t)(uint32_t)r << 32) | (uint32_t)v;
+            if constexpr (KEEP) {
+                uint64_t* q = want ? bout + r : gspare;
+                *q = ((uint64_t)epoch << 32) | (uint32_t)v;
+            }
+        } else if constexpr (OUT == kIoGlobal) {
+            uint64_t* q = want ? bout + r : gspare;
+            __hip_atomic_store(q, ((uint64_t)epoch << 32) | (uint32_t)v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     __device__ __forceinline__ void fail() const {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -140,23 +203,60 @@ struct TaggedIO {
     __device__ __forceinline__ bool failed() const {
         return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
+    // The output ring's reader progress, read one group before it is needed.
+    __device__ __forceinline__ int room_probe() const {
+        if constexpr (OUT == kIoLds) return *(volatile lds_i32*)cout;
+        else return 0;
+    }
+    // Before rows up to r_hi go out: the ring slots they take must be free.
+    // `probe` is a possibly stale (hence lower) reading of the reader's progress.
+    __device__ __forceinline__ void wait_room(int r_hi, int& probe) const {
+        if constexpr (OUT == kIoLds) {
+            const int need = r_hi - kRing;
+            for (int spin = 0; probe < need; ++spin) {
+                if (spin >= kSpinLimit) {
+                    fail();
+                    return;
+                }
+                if ((spin & 31) == 31 && failed()) return;
+                __builtin_amdgcn_s_sleep(1);
+                probe = *(volatile lds_i32*)cout;
+            }
+        }
+    }
+    // After a refill: every row up to r_hi has been read from the input ring.
+    __device__ __forceinline__ void mark_consumed(int r_hi) const {
+        if constexpr (IN == kIoLds) *(volatile lds_i32*)cin = r_hi;
+    }
 };
 
-constexpr int kSpinLimit = 1 << 16;  // polling rounds before a boundary wait gives up
-
 // Load slot r (for the lanes with `want`) until every such lane sees a ready
-// slot.  The loop condition is wave-uniform.
+// slot.  The loop condition is wave-uniform.  The shared failure flag is a
+// device-scope load (a round trip to L2), so it is checked only every 32 polls.
 template <class IO>
 __device__ __forceinline__ typename IO::Slot wait_slot(const IO& io, int r, bool want) {
     typename IO::Slot x = io.load(r, want);
     for (int spin = 0; spin < kSpinLimit; ++spin) {
         if (__builtin_amdgcn_ballot_w64(!io.ready(x, r, want)) == 0) return x;
-        if (io.failed()) return x;  // another wait already gave up: drain quickly
-        __builtin_amdgcn_s_sleep(2);
+        if ((spin & 31) == 31 && io.failed()) return x;  // another wait gave up: drain quickly
+        __builtin_amdgcn_s_sleep(1);
         x = io.load(r, want);
     }
     io.fail();
     return x;
+}
+
+// Row word of grid row r of the sweep (r in 1..m), from its base code x.
+__device__ __forceinline__ uint32_t table_word(int r, int m, uint32_t x, int kdm, int kdx) {
+    return (r >= 1 && r <= m) ? row_word(x, kdm, kdx) : kSentinelWord;
+}
+
+// Write row r's word to the table (index r & 255, and its mirror copy when the
+// index is below kGroup), or, for lanes with `skip`, to the spare word.
+__device__ __forceinline__ void table_put(uint32_t* tab, int r, uint32_t w, bool skip) {
+    const int i = r & (kTabRows - 1);
+    tab[skip ? kTabSpare : i] = w;
+    tab[skip ? kTabSpare : (i < kGroup ? kTabRows + i : i)] = w;
 }
 
 // Sweep one strip.  Returns, per lane, V (or W) of its column `ksel` after
@@ -174,66 +274,56 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
     const int lane = lane_id();
     const bool lane0 = (lane == 0);
     int32_t V[C];
-    uint32_t acc[C];
+    uint32_t acc0[C], acc1[C];  // direction words of the group's two halves
     uint32_t bcode[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         V[k] = vtop;
-        acc[k] = 0;
+        acc0[k] = 0;
+        acc1[k] = 0;
         int j = j0 + C * lane + k;
         bcode[k] = (j < n) ? (uint32_t)(b[j] & 3) : 0u;
     }
     int32_t Dg = lane0 ? dg0 : vtop;
-    int32_t R = io.value(wait_slot(io, lane + 1, lane < 16), lane + 1);
-    // boundary values for the refill of lanes 0..15 at the end of group 0
-    int rin = 16 + 1 + lane;
-    typename IO::Slot Rin = io.load(rin, lane < 16);
 
-    const int NG = groups_for_rows(m);
-    // window 0 covers groups [0, 8): rows [-63, 129)
-    int g0 = 0;
-    int cur = 0;
-    write_window(lds, a, m, -63, kdm, kdx, lane);
-    // prefetch the next window's symbols
-    uint8_t pf[kWinRows / kWave];
-#pragma unroll
-    for (int e = 0; e < kWinRows / kWave; ++e) {
-        int r = 16 * kWinGroups - 63 + lane + kWave * e;
-        pf[e] = (r >= 1 && r <= m) ? a[r - 1] : (uint8_t)0xFF;
+    // Row table: rows -63 .. 64 serve groups 0 and 1; each group end writes the
+    // rows of the group after next, from base codes loaded two groups earlier.
+    for (int p = lane; p < 128; p += kWave) {
+        const int r = p - 63;
+        table_put(lds, r, table_word(r, m, (r >= 1 && r <= m) ? a[r - 1] : 0u, kdm, kdx), false);
     }
+    const int mc = max(m, 1);
+    uint32_t pfa = a[min(max(65 + lane, 1), mc) - 1];  // rows 65..96: written at the end of group 0
+    uint32_t pfb = a[min(max(97 + lane, 1), mc) - 1];  // rows 97..128: end of group 1
+    __builtin_amdgcn_wave_barrier();
 
+    int32_t R = io.value(wait_slot(io, lane + 1, lane < kGroup), lane + 1);
+    // Refill of lanes 0..31 at the end of group g: rows 32g + 33 + lane.  The
+    // group loop runs in pairs so that even groups keep their prefetched
+    // refill and table bytes in one set of registers and odd groups in
+    // another, each reloaded in place two groups ahead: a loop-carried copy of
+    // a register with a load in flight would make the compiler wait for it.
+    int rin = kGroup + 1 + lane;
+    typename IO::Slot RinA = 0, RinB = 0;
+    if constexpr (IO::kPrefetch >= 1) RinA = io.load(rin, lane < kGroup);
+    if constexpr (IO::kPrefetch == 2) RinB = io.load(rin + kGroup, lane < kGroup);
+    int probe = io.room_probe();
+
+    const int NG = sweep_groups(m);
     const int8_t* lds8 = reinterpret_cast<const int8_t*>(lds);
-    for (int g = 0; g < NG; ++g) {
-        int gg = g - g0;
-        if (gg == kWinGroups) {
-            // switch windows: materialise the prefetched rows, then prefetch the next
-            cur ^= 1;
-            g0 += kWinGroups;
-            gg = 0;
-            uint32_t* win = lds + cur * kWinRows;
-#pragma unroll
-            for (int e = 0; e < kWinRows / kWave; ++e) {
-                int p = lane + kWave * e;
-                win[p] = (pf[e] == 0xFF) ? kSentinelWord : row_word(pf[e], kdm, kdx);
-            }
-#pragma unroll
-            for (int e = 0; e < kWinRows / kWave; ++e) {
-                int r = 16 * (g0 + kWinGroups) - 63 + lane + kWave * e;
-                pf[e] = (r >= 1 && r <= m) ? a[r - 1] : (uint8_t)0xFF;
-            }
-        }
-        // byte address of (row of step 16g, this lane, column k) in the window;
-        // the mask shows the compiler the address is non-negative so the
-        // per-step offsets 4u fold into the ds_read immediate
-        const uint32_t base = (uint32_t)(cur * kWinRows * 4 + 4 * (64 - lane) + 64 * gg);
+
+    // 16 steps starting at step 32g + 16h, tags into acc[]
+    auto half = [&](const int g, const int h, uint32_t (&acc)[C]) {
+        // byte address of (row of the half's first step, this lane, column k) in
+        // the table; the per-step offsets 4u fold into the ds_read immediate
+        const uint32_t base = 4u * (uint32_t)((kGroup * g + 16 * h - lane + 1) & (kTabRows - 1));
         uint32_t addr[C];
 #pragma unroll
-        for (int k = 0; k < C; ++k) addr[k] = (base + bcode[k]) & 0x7FFFu;
-
+        for (int k = 0; k < C; ++k) addr[k] = base + bcode[k];
 
         // Narrow strips have too little work per step to hide the LDS latency
-        // behind other waves, so their whole group of table reads is issued up
-        // front; wide strips read one step at a time.
+        // behind other waves, so the half's table reads are issued up front;
+        // wide strips read one step at a time.
         constexpr bool kHoist = (C <= 2);
         int32_t kdh[kHoist ? 16 : 1][C];
         if constexpr (kHoist) {
@@ -277,28 +367,65 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
             R = dpp_from_right(tail, R);
             Dg = Lr;
         }
-        __builtin_amdgcn_sched_barrier(0);  // keep the refill's wait after the steps
-        // Group end.  Take this group's refill, then issue the next group's
-        // boundary load before this group's stores: vector-memory operations
-        // retire in order, so a load queued behind a device-coherent store
-        // would make the next refill wait for that store's round trip.
-        if (__builtin_amdgcn_ballot_w64(!io.ready(Rin, rin, lane < 16)) != 0)
-            Rin = wait_slot(io, rin, lane < 16);
-        const int32_t refill = io.value(Rin, rin);
-        rin += 16;
-        Rin = io.load(rin, lane < 16);
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (DIRS) {
-            uint32_t* dst = dirs + ((size_t)g * kWave + lane) * C;
+    };
+
+    auto store_dirs = [&](uint32_t* dst, const uint32_t (&acc)[C]) {
+        // a lane's C words are contiguous (and 4C-byte aligned): store them with
+        // the widest stores that fit
+        if constexpr (C % 4 == 0) {
+#pragma unroll
+            for (int k = 0; k < C; k += 4)
+                *reinterpret_cast<uint4*>(dst + k) = make_uint4(acc[k], acc[k + 1], acc[k + 2], acc[k + 3]);
+        } else if constexpr (C == 2) {
+            *reinterpret_cast<uint2*>(dst) = make_uint2(acc[0], acc[1]);
+        } else {
 #pragma unroll
             for (int k = 0; k < C; ++k) dst[k] = acc[k];
         }
+    };
+
+    // Rin: this group's refill; Rnext: the next group's (the other parity's
+    // register, loaded here when the prefetch is one group deep)
+    auto group = [&](const int g, typename IO::Slot& Rin, typename IO::Slot& Rnext, uint32_t& pf) {
+        half(g, 0, acc0);
+        half(g, 1, acc1);
+        __builtin_amdgcn_sched_barrier(0);  // keep the refill's wait after the steps
+        // Group end: take this group's refill, issue the loads of later groups,
+        // then the stores (all branch-free, see above).
+        if constexpr (IO::kPrefetch == 0) Rin = io.load(rin, lane < kGroup);
+        if (__builtin_amdgcn_ballot_w64(!io.ready(Rin, rin, lane < kGroup)) != 0)
+            Rin = wait_slot(io, rin, lane < kGroup);
+        const int32_t refill = io.value(Rin, rin);
+        // rin is per lane (rin + lane); the refill ends at lane 31's row
+        io.mark_consumed(uniform(rin) + kGroup - 1);
+        if constexpr (IO::kPrefetch == 1) Rnext = io.load(rin + kGroup, lane < kGroup);
+        if constexpr (IO::kPrefetch == 2) Rin = io.load(rin + 2 * kGroup, lane < kGroup);
+        rin += kGroup;
         {
-            const int r = 16 * g + lane - 111;
-            io.store(r, DIRS ? R - 1 : R, lane >= 48 && r >= 1 && r <= m);
+            const int r = kGroup * g + 2 * kGroup + 1 + lane;  // table rows of group g + 2
+            table_put(lds, r, table_word(r, m, pf, kdm, kdx), lane >= kGroup);
+            pf = a[min(max(r + 2 * kGroup, 1), mc) - 1];  // rows of group g + 4, written at the end of g + 2
         }
-        R = (lane < 16) ? refill : R;
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (DIRS) {
+            store_dirs(dirs + ((size_t)(2 * g) * kWave + lane) * C, acc0);
+            store_dirs(dirs + ((size_t)(2 * g + 1) * kWave + lane) * C, acc1);
+        }
+        {
+            // lanes 32..63 hold the group's outputs: rows 32g - 63 .. 32g - 32
+            const int r = kGroup * g + lane - 95;
+            io.wait_room(kGroup * g - 32, probe);
+            io.store(r, DIRS ? R - 1 : R, lane >= kGroup && r >= 1 && r <= m);
+            probe = io.room_probe();
+        }
+        R = (lane < kGroup) ? refill : R;
+    };
+    int g = 0;
+    for (; g + 1 < NG; g += 2) {
+        group(g, RinA, RinB, pfa);
+        group(g + 1, RinB, RinA, pfb);
     }
+    if (g < NG) group(g, RinA, RinB, pfa);
     int32_t out = V[0];
 #pragma unroll
     for (int k = 1; k < C; ++k)
