@@ -201,36 +201,51 @@ __global__ __launch_bounds__(256) void k_mlp_backward_act(int32_t rows, const fl
     dz1[(int64_t)r * kH + lane] = (z1[(int64_t)r * kH + lane] > 0.f) ? acc : 0.f;
 }
 
-// Parameter gradients: one thread per parameter, summing the batch rows in
-// order (deterministic, no atomics).
-__global__ __launch_bounds__(256) void k_mlp_wgrad(int32_t rows, const float* x, const int32_t* rows_idx,
-                                                   const float* z1, const float* z2, const float* dy,
-                                                   const float* dz1, const float* dz2, float* grad) {
+// Parameter gradients in two passes, both in a fixed order (deterministic,
+// no atomics): kRowChunks partial sums over consecutive row chunks, one
+// thread per (parameter, chunk), then their sum per parameter.
+constexpr int kRowChunks = 8;
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad_part(int32_t rows, const float* x, const int32_t* rows_idx,
+                                                        const float* z1, const float* z2, const float* dy,
+                                                        const float* dz1, const float* dz2, float* part) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int chunk = blockIdx.y;
     if (p >= NW_MLP_PARAMS) return;
+    const int per = (rows + kRowChunks - 1) / kRowChunks;
+    const int r_lo = chunk * per, r_hi = min(rows, r_lo + per);
     float acc = 0.f;
     if (p < kOffB1) {
         const int j = p / kIn, i = p - j * kIn;
-        for (int r = 0; r < rows; ++r) {
+        for (int r = r_lo; r < r_hi; ++r) {
             const int64_t src = rows_idx ? rows_idx[r] : r;
             acc = fmaf(dz1[(int64_t)r * kH + j], x[src * kIn + i], acc);
         }
     } else if (p < kOffW2) {
         const int j = p - kOffB1;
-        for (int r = 0; r < rows; ++r) acc += dz1[(int64_t)r * kH + j];
+        for (int r = r_lo; r < r_hi; ++r) acc += dz1[(int64_t)r * kH + j];
     } else if (p < kOffB2) {
         const int q = p - kOffW2, j = q / kH, k = q - j * kH;
-        for (int r = 0; r < rows; ++r)
+        for (int r = r_lo; r < r_hi; ++r)
             acc = fmaf(dz2[(int64_t)r * kH + j], fmaxf(z1[(int64_t)r * kH + k], 0.f), acc);
     } else if (p < kOffW3) {
         const int j = p - kOffB2;
-        for (int r = 0; r < rows; ++r) acc += dz2[(int64_t)r * kH + j];
+        for (int r = r_lo; r < r_hi; ++r) acc += dz2[(int64_t)r * kH + j];
     } else if (p < kOffB3) {
         const int j = p - kOffW3;
-        for (int r = 0; r < rows; ++r) acc = fmaf(dy[r], fmaxf(z2[(int64_t)r * kH + j], 0.f), acc);
+        for (int r = r_lo; r < r_hi; ++r) acc = fmaf(dy[r], fmaxf(z2[(int64_t)r * kH + j], 0.f), acc);
     } else {
-        for (int r = 0; r < rows; ++r) acc += dy[r];
+        for (int r = r_lo; r < r_hi; ++r) acc += dy[r];
     }
+    part[(int64_t)chunk * NW_MLP_PARAMS + p] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad_sum(const float* part, float* grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NW_MLP_PARAMS) return;
+    float acc = 0.f;
+#pragma unroll
+    for (int c = 0; c < kRowChunks; ++c) acc += part[(int64_t)c * NW_MLP_PARAMS + p];
     grad[p] = acc;
 }
 
@@ -322,8 +337,8 @@ int launch_quantize(const float* params, uint16_t* wq, hipStream_t st) {
 
 size_t mlp_train_workspace_bytes(int32_t batch) {
     const size_t b = (size_t)std::max(batch, 1);
-    // yhat, dy, loss_row: b each; z1, z2, dz1, dz2: b*64 each; grad
-    return align_up((3 * b + 4 * b * kH + NW_MLP_PARAMS) * sizeof(float), 256);
+    // yhat, dy, loss_row: b each; z1, z2, dz1, dz2: b*64 each; grad; partial sums
+    return align_up((3 * b + 4 * b * kH + (1 + kRowChunks) * (size_t)NW_MLP_PARAMS) * sizeof(float), 256);
 }
 
 int launch_mlp_train_step(nw_mlp* mlp, int32_t batch, const float* x, const float* target,
@@ -337,7 +352,9 @@ int launch_mlp_train_step(nw_mlp* mlp, int32_t batch, const float* x, const floa
     float* z2 = z1 + (size_t)batch * kH;
     float* dz1 = z2 + (size_t)batch * kH;
     float* dz2 = dz1 + (size_t)batch * kH;
-    float* grad = grad_out ? grad_out : dz2 + (size_t)batch * kH;
+    float* grad_ws = dz2 + (size_t)batch * kH;
+    float* part = grad_ws + NW_MLP_PARAMS;
+    float* grad = grad_out ? grad_out : grad_ws;
     {
         ProfScope ps("nw_mlp_train_forward", st);
         hipLaunchKernelGGL(k_mlp_forward, dim3(forward_grid(batch, di)), dim3(256), 0, st, batch, x, rows_idx,
@@ -348,8 +365,9 @@ int launch_mlp_train_step(nw_mlp* mlp, int32_t batch, const float* x, const floa
         hipLaunchKernelGGL(k_mlp_backward_act, dim3(blocks_for(batch, 4)), dim3(256), 0, st, batch, target,
                            rows_idx, yhat, z1, z2, (const uint16_t*)mlp->params_bf16, tau, dy, dz1, dz2,
                            loss_row);
-        hipLaunchKernelGGL(k_mlp_wgrad, dim3(blocks_for(NW_MLP_PARAMS, 256)), dim3(256), 0, st, batch, x,
-                           rows_idx, z1, z2, dy, dz1, dz2, grad);
+        hipLaunchKernelGGL(k_mlp_wgrad_part, dim3(blocks_for(NW_MLP_PARAMS, 256), kRowChunks), dim3(256), 0, st,
+                           batch, x, rows_idx, z1, z2, dy, dz1, dz2, part);
+        hipLaunchKernelGGL(k_mlp_wgrad_sum, dim3(blocks_for(NW_MLP_PARAMS, 256)), dim3(256), 0, st, part, grad);
     }
     if (loss) hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, batch, loss_row, loss);
     if (lr > 0.f) {

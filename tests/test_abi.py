@@ -81,7 +81,7 @@ def test_band_model_host_checks():
     sz = ctypes.c_size_t(0)
     assert L.nw_mlp_train_workspace_size(0, ctypes.byref(sz)) == nwp.NW_EINVAL
     assert L.nw_mlp_train_workspace_size(256, ctypes.byref(sz)) == nwp.NW_OK
-    assert sz.value >= (3 * 256 + 4 * 256 * 64 + nwp.MLP_PARAMS) * 4
+    assert sz.value >= (3 * 256 + 4 * 256 * 64 + 9 * nwp.MLP_PARAMS) * 4
     # labels need an applicable certificate: 2*gap < max(match, mismatch)
     assert L.nw_band_labels(4, vp(1), vp(1), vp(1), nwp.Scoring(1, -1, 1), vp(1), vp(1), vp(0)) == nwp.NW_EINVAL
     assert L.nw_band_labels(-1, vp(1), vp(1), vp(1), P, vp(1), vp(1), vp(0)) == nwp.NW_EINVAL
