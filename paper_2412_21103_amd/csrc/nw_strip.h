@@ -213,6 +213,8 @@ struct CoopIO {
     __device__ __forceinline__ void wait_room(int r_hi, int& probe) const {
         if constexpr (OUT == kIoLds) {
             const int need = r_hi - kRing;
+            probe = uniform(probe);
+            if (__builtin_expect(probe >= need, 1)) return;
             for (int spin = 0; probe < need; ++spin) {
                 if (spin >= kSpinLimit) {
                     fail();
@@ -220,7 +222,7 @@ struct CoopIO {
                 }
                 if ((spin & 31) == 31 && failed()) return;
                 __builtin_amdgcn_s_sleep(1);
-                probe = *(volatile lds_i32*)cout;
+                probe = uniform(*(volatile lds_i32*)cout);
             }
         }
     }
@@ -390,23 +392,16 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
         half(g, 0, acc0);
         half(g, 1, acc1);
         __builtin_amdgcn_sched_barrier(0);  // keep the refill's wait after the steps
-        // Group end: take this group's refill, issue the loads of later groups,
-        // then the stores (all branch-free, see above).
+        // Group end: issue a fresh refill read, do the stores (all branch-free),
+        // then take the refill and issue the loads of later groups.  The
+        // outputs go out before the wait for input, so a wave that waits
+        // holds up nobody downstream.
         if constexpr (IO::kPrefetch == 0) Rin = io.load(rin, lane < kGroup);
-        if (__builtin_amdgcn_ballot_w64(!io.ready(Rin, rin, lane < kGroup)) != 0)
-            Rin = wait_slot(io, rin, lane < kGroup);
-        const int32_t refill = io.value(Rin, rin);
-        // rin is per lane (rin + lane); the refill ends at lane 31's row
-        io.mark_consumed(uniform(rin) + kGroup - 1);
-        if constexpr (IO::kPrefetch == 1) Rnext = io.load(rin + kGroup, lane < kGroup);
-        if constexpr (IO::kPrefetch == 2) Rin = io.load(rin + 2 * kGroup, lane < kGroup);
-        rin += kGroup;
         {
             const int r = kGroup * g + 2 * kGroup + 1 + lane;  // table rows of group g + 2
             table_put(lds, r, table_word(r, m, pf, kdm, kdx), lane >= kGroup);
             pf = a[min(max(r + 2 * kGroup, 1), mc) - 1];  // rows of group g + 4, written at the end of g + 2
         }
-        __builtin_amdgcn_sched_barrier(0);
         if constexpr (DIRS) {
             store_dirs(dirs + ((size_t)(2 * g) * kWave + lane) * C, acc0);
             store_dirs(dirs + ((size_t)(2 * g + 1) * kWave + lane) * C, acc1);
@@ -418,6 +413,15 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
             io.store(r, DIRS ? R - 1 : R, lane >= kGroup && r >= 1 && r <= m);
             probe = io.room_probe();
         }
+        __builtin_amdgcn_sched_barrier(0);
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(!io.ready(Rin, rin, lane < kGroup)) != 0, 0))
+            Rin = wait_slot(io, rin, lane < kGroup);
+        const int32_t refill = io.value(Rin, rin);
+        // rin is per lane (rin + lane); the refill ends at lane 31's row
+        io.mark_consumed(uniform(rin) + kGroup - 1);
+        if constexpr (IO::kPrefetch == 1) Rnext = io.load(rin + kGroup, lane < kGroup);
+        if constexpr (IO::kPrefetch == 2) Rin = io.load(rin + 2 * kGroup, lane < kGroup);
+        rin += kGroup;
         R = (lane < kGroup) ? refill : R;
     };
     int g = 0;
