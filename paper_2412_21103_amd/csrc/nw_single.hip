@@ -266,7 +266,103 @@ __global__ __launch_bounds__(kCoopThreads) void k_tb_spec(TbArgs T) {
     }
 }
 
-// One wave chains the strips from the last to the first.
+// Re-walk strip s from its true entry row e (at the strip's last column)
+// until the walk meets the strip's speculative walk, recorded per column as
+// the row range lo..hi it visited and the move index at which it entered the
+// column, or leaves the strip.  The re-walk's moves go to the strip's rw
+// buffer.  Returns whether it met the speculative walk; sets rw_len, seg_from
+// (how many speculative moves the merged walk skips), exit_row (if it did not
+// meet), and error (a corrupt tag).
+template <int C>
+__device__ bool rewalk(const TbArgs& T, int s, int e, int32_t (*col)[kWave * C], DirWindow<C>& win, int& rw_len,
+                       int& seg_from, int& exit_row, int& error) {
+    constexpr int kCols = kWave * C;
+    const int lane = lane_id();
+    const int j_lo = s * kCols + 1;
+    const int32_t* rec = T.info + (int64_t)s * T.info_stride + kInfoHead;
+    for (int c = lane; c < kCols; c += kWave) {
+        col[0][c] = rec[c];
+        col[1][c] = rec[kCols + c];
+        col[2][c] = rec[2 * kCols + c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint8_t* out = T.rw + (int64_t)s * T.seg_stride;
+    int i = e, j = min((s + 1) * kCols, T.n);
+    bool merged = false;
+    rw_len = 0;
+    while (j >= j_lo) {
+        const int c = j - j_lo;
+        const int clo = col[0][c], chi = col[1][c];
+        if (chi >= 0 && clo <= i && i <= chi) {
+            seg_from = col[2][c] + (chi - i);
+            merged = true;
+            break;
+        }
+        int mv = 3;
+        if (i > 0) {
+            const int tag = win.tag(i, j);
+            if (tag == 0) {
+                error = 1;
+                break;
+            }
+            mv = 4 - tag;
+        }
+        out[rw_len++] = (uint8_t)mv;
+        if (mv == 1) {
+            --i;
+            --j;
+        } else if (mv == 2) {
+            --i;
+        } else {
+            --j;
+        }
+    }
+    exit_row = i;
+    __builtin_amdgcn_wave_barrier();
+    return merged;
+}
+
+// All strips at once, one wave each.  If every re-walk meets its strip's
+// speculative walk, the true path leaves each strip where that walk leaves
+// it, so the entry row of strip s is the speculative exit row of strip s + 1
+// and no strip has to wait for another.  A re-walk that leaves its strip
+// without meeting the walk breaks that assumption: the flag it raises sends
+// k_tb_fix down the sequential chain instead.
+template <int C>
+__global__ __launch_bounds__(kCoopThreads) void k_tb_merge(TbArgs T) {
+    constexpr int kCols = kWave * C;
+    __shared__ uint32_t win_lds[kCoopWaves][kWave * C];
+    __shared__ int32_t col_lds[kCoopWaves][3][kCols];
+    const int wave = threadIdx.x >> 6;
+    const int s = blockIdx.x * kCoopWaves + wave;
+    if (s >= T.nstrips) return;
+    if (__hip_atomic_load(T.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    const int32_t* rec = T.info + (int64_t)s * T.info_stride;
+    const int len = rec[0], start = rec[1], loR = rec[3], hiR = rec[4];
+    int error = rec[5];
+    const int e = (s == T.nstrips - 1) ? T.m : T.info[(int64_t)(s + 1) * T.info_stride + 2];
+    int rw_len = 0, seg_from = 0, exit_row = 0;
+    if (s == T.nstrips - 1) {
+        seg_from = 0;
+    } else if (hiR >= 0 && loR <= e && e <= hiR) {
+        seg_from = start - e;
+    } else {
+        DirWindow<C> win(T.dirs, T.G, win_lds[wave]);
+        if (!rewalk<C>(T, s, e, col_lds[wave], win, rw_len, seg_from, exit_row, error))
+            __hip_atomic_store(T.summary + 4, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (error) __hip_atomic_store(T.summary + 5, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane_id() == 0) {
+        int32_t* f = T.fix + 4 * (int64_t)s;
+        f[0] = rw_len;
+        f[1] = seg_from;
+        f[2] = rw_len + (len - seg_from);
+    }
+}
+
+// Offsets of every strip's segment; when some re-walk left its strip without
+// meeting the speculative walk, one wave first chains the strips from the
+// last to the first instead.
 template <int C>
 __global__ __launch_bounds__(kWave) void k_tb_fix(TbArgs T) {
     constexpr int kCols = kWave * C;
@@ -280,90 +376,59 @@ __global__ __launch_bounds__(kWave) void k_tb_fix(TbArgs T) {
     DirWindow<C> win(T.dirs, T.G, win_lds);
     int e = T.m;     // entry row of the current strip
     int error = 0;
-    // headers arrive 64 strips at a time: lane q holds strip (base - q)
-    int base = T.nstrips - 1;
-    int32_t h_len = 0, h_start = 0, h_exit = 0, h_lo = 0, h_hi = 0, h_bad = 0;
-    auto load_chunk = [&](int b) {
-        const int sq = b - lane;
-        if (sq >= 0) {
-            const int32_t* rec = T.info + (int64_t)sq * T.info_stride;
-            h_len = rec[0];
-            h_start = rec[1];
-            h_exit = rec[2];
-            h_lo = rec[3];
-            h_hi = rec[4];
-            h_bad = rec[5];
-        }
-    };
-    load_chunk(base);
-    for (int s = T.nstrips - 1; s >= 0; --s) {
-        if (base - s >= kWave) {
-            base = s;
-            load_chunk(base);
-        }
-        const int ql = base - s;
-        const int len = __builtin_amdgcn_readlane(h_len, ql);
-        const int start = __builtin_amdgcn_readlane(h_start, ql);
-        const int sexit = __builtin_amdgcn_readlane(h_exit, ql);
-        const int loR = __builtin_amdgcn_readlane(h_lo, ql);
-        const int hiR = __builtin_amdgcn_readlane(h_hi, ql);
-        error |= __builtin_amdgcn_readlane(h_bad, ql);
-        int rw_len = 0, seg_from = 0, exit_row = sexit;
-        if (s == T.nstrips - 1) {
-            seg_from = 0;
-        } else if (hiR >= 0 && loR <= e && e <= hiR) {
-            seg_from = start - e;
-        } else {
-            // walk from the true entry until the speculative walk is met
-            const int j_lo = s * kCols + 1;
-            const int32_t* rec = T.info + (int64_t)s * T.info_stride + kInfoHead;
-            for (int c = lane; c < kCols; c += kWave) {
-                col_lds[0][c] = rec[c];
-                col_lds[1][c] = rec[kCols + c];
-                col_lds[2][c] = rec[2 * kCols + c];
+    if (__hip_atomic_load(T.summary + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        // k_tb_merge has placed every strip: the path reaches column 0 where
+        // strip 0's speculative walk does
+        error = __hip_atomic_load(T.summary + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        e = T.info[2];
+    } else {
+        // headers arrive 64 strips at a time: lane q holds strip (base - q)
+        int base = T.nstrips - 1;
+        int32_t h_len = 0, h_start = 0, h_exit = 0, h_lo = 0, h_hi = 0, h_bad = 0;
+        auto load_chunk = [&](int b) {
+            const int sq = b - lane;
+            if (sq >= 0) {
+                const int32_t* rec = T.info + (int64_t)sq * T.info_stride;
+                h_len = rec[0];
+                h_start = rec[1];
+                h_exit = rec[2];
+                h_lo = rec[3];
+                h_hi = rec[4];
+                h_bad = rec[5];
             }
-            __builtin_amdgcn_wave_barrier();
-            uint8_t* out = T.rw + (int64_t)s * T.seg_stride;
-            int i = e, j = min((s + 1) * kCols, T.n);
-            bool merged = false;
-            while (j >= j_lo) {
-                const int c = j - j_lo;
-                const int clo = col_lds[0][c], chi = col_lds[1][c];
-                if (chi >= 0 && clo <= i && i <= chi) {
-                    seg_from = col_lds[2][c] + (chi - i);
-                    merged = true;
-                    break;
-                }
-                int mv = 3;
-                if (i > 0) {
-                    const int tag = win.tag(i, j);
-                    if (tag == 0) {
-                        error = 1;
-                        break;
-                    }
-                    mv = 4 - tag;
-                }
-                out[rw_len++] = (uint8_t)mv;
-                if (mv == 1) {
-                    --i;
-                    --j;
-                } else if (mv == 2) {
-                    --i;
-                } else {
-                    --j;
+        };
+        load_chunk(base);
+        for (int s = T.nstrips - 1; s >= 0; --s) {
+            if (base - s >= kWave) {
+                base = s;
+                load_chunk(base);
+            }
+            const int ql = base - s;
+            const int len = __builtin_amdgcn_readlane(h_len, ql);
+            const int start = __builtin_amdgcn_readlane(h_start, ql);
+            const int sexit = __builtin_amdgcn_readlane(h_exit, ql);
+            const int loR = __builtin_amdgcn_readlane(h_lo, ql);
+            const int hiR = __builtin_amdgcn_readlane(h_hi, ql);
+            error |= __builtin_amdgcn_readlane(h_bad, ql);
+            int rw_len = 0, seg_from = 0, exit_row = sexit;
+            if (s == T.nstrips - 1) {
+                seg_from = 0;
+            } else if (hiR >= 0 && loR <= e && e <= hiR) {
+                seg_from = start - e;
+            } else {
+                // walk from the true entry until the speculative walk is met
+                int rexit = 0;
+                if (!rewalk<C>(T, s, e, col_lds, win, rw_len, seg_from, rexit, error)) {
+                    seg_from = len;
+                    exit_row = rexit;
                 }
             }
-            if (!merged) {
-                seg_from = len;
-                exit_row = i;
-            }
-            __builtin_amdgcn_wave_barrier();
+            int32_t* f = T.fix + 4 * (int64_t)s;
+            f[0] = rw_len;
+            f[1] = seg_from;
+            f[2] = rw_len + (len - seg_from);
+            e = exit_row;
         }
-        int32_t* f = T.fix + 4 * (int64_t)s;
-        f[0] = rw_len;
-        f[1] = seg_from;
-        f[2] = rw_len + (len - seg_from);
-        e = exit_row;
     }
     // e is now the row at which the path reaches column 0: that many vertical
     // moves come first in forward order, then strips 0, 1, ... in turn
@@ -549,6 +614,10 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
         {
             ProfScope ps("nw_tb_spec", st);
             hipLaunchKernelGGL(k_tb_spec<kCoopC>, dim3(blocks), dim3(kCoopThreads), 0, st, T);
+        }
+        {
+            ProfScope ps("nw_tb_merge", st);
+            hipLaunchKernelGGL(k_tb_merge<kCoopC>, dim3(blocks), dim3(kCoopThreads), 0, st, T);
         }
         {
             ProfScope ps("nw_tb_fix", st);

@@ -146,6 +146,39 @@ def test_cooperative_single_pair_shapes():
         check_pair(a, b, P, "coop")
 
 
+def test_cooperative_traceback_both_chains():
+    # The long-pair traceback places every strip's segment at once when each
+    # re-walk from a strip's true entry meets that strip's speculative walk,
+    # and falls back to chaining the strips one by one when one does not.
+    # Periodic and unrelated sequences have parallel co-optimal paths that
+    # never meet inside a strip, so they take the fallback; a related pair
+    # takes the parallel placement.  The chain taken is read from the
+    # workspace (its header: a fallback flag at int32 index 32 + 4).
+    import torch
+    import paper_2412_21103_amd as nwp
+    rng = np.random.default_rng(77)
+    unit = random_seq(rng, 20)
+    a_rep = np.tile(unit, 160)[:3000]
+    b_rep = np.concatenate([random_seq(rng, 11), mutate(rng, a_rep, 0.05)])[:3003]
+    a_rel = random_seq(rng, 3000)
+    b_rel = mutate(rng, a_rel, 0.3)
+    cases = [("periodic", a_rep, b_rep, 1), ("unrelated", random_seq(rng, 3000), random_seq(rng, 2900), 1),
+             ("related", a_rel, b_rel, None)]
+    for tag, a, b, want in cases:
+        m, n = len(a), len(b)
+        ws = torch.zeros(nwp.align_workspace_size(m, n), dtype=torch.uint8, device="cuda")
+        s, p, pl = nwp.align(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), P, workspace=ws)
+        torch.cuda.synchronize()
+        fallback = int(ws[128 + 16:128 + 20].cpu().numpy().view(np.int32)[0])
+        say(f"traceback chain {tag} {m}x{n}: fallback={fallback}")
+        s_ref, p_ref = oracle.align(a, b, P)
+        k = int(pl.item())
+        assert int(s.item()) == s_ref, tag
+        assert p[:k].cpu().numpy().tolist() == p_ref.tolist(), tag
+        if want is not None:
+            assert fallback == want, tag
+
+
 def test_long_pair_full_size():
     from workloads import config_long_pair
     p = config_long_pair()
