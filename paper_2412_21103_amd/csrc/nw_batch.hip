@@ -17,7 +17,11 @@ namespace nw {
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlockThreads = kWave * kWavesPerBlock;
-constexpr int kBlocksPerCu = 2;
+// Resident blocks of four waves per CU (= waves per SIMD).  Score-only sweeps
+// fit in 128 VGPRs and run 4 per SIMD, which hides their LDS and boundary
+// latencies (all-pairs 83 -> 67 ms); sweeps with directions keep 2: more would
+// stretch each pair's wave, and the largest pairs already set the makespan.
+constexpr int blocks_per_cu(bool dirs) { return dirs ? 2 : 4; }
 constexpr int kBuckets = 64;
 
 struct KArgs {
@@ -244,7 +248,7 @@ __device__ __forceinline__ int64_t walk_any(int C, const uint32_t* dirs, int m, 
 }
 
 template <bool DIRS, bool ALLPAIRS, bool BANDED>
-__global__ __launch_bounds__(kBlockThreads) void k_batch(KArgs A) {
+__global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KArgs A) {
     __shared__ uint32_t smem[kWavesPerBlock][StripShape<8>::kLdsWords];
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
@@ -439,7 +443,7 @@ static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const Device
                                                        (size_t)L.rev_stride);
     const size_t fixed = align_up(kHeaderBytes + (size_t)std::max(njobs, 1) * 4, 256) + 3 * 256;
     const int64_t want = ((int64_t)njobs + kWavesPerBlock - 1) / kWavesPerBlock;
-    int64_t grid = std::min<int64_t>(std::max<int64_t>(want, 1), (int64_t)di.cus * kBlocksPerCu);
+    int64_t grid = std::min<int64_t>(std::max<int64_t>(want, 1), (int64_t)di.cus * blocks_per_cu(dirs));
     const size_t budget = std::min(ws_limit, fixed + std::max(kSlotBudget, per_block));
     if (budget < fixed + per_block) {
         L.total = fixed + per_block;  // too small: the caller gets NW_ENOSPC

@@ -286,6 +286,9 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
         int j = j0 + C * lane + k;
         bcode[k] = (j < n) ? (uint32_t)(b[j] & 3) : 0u;
     }
+    uint32_t onehot[C];  // 1 in byte b[j] of column j: selects that row-word byte in v_dot4
+#pragma unroll
+    for (int k = 0; k < C; ++k) onehot[k] = 1u << (8 * bcode[k]);
     int32_t Dg = lane0 ? dg0 : vtop;
 
     // Row table: rows -63 .. 64 serve groups 0 and 1; each group end writes the
@@ -316,23 +319,20 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
 
     // 16 steps starting at step 32g + 16h, tags into acc[]
     auto half = [&](const int g, const int h, uint32_t (&acc)[C]) {
-        // byte address of (row of the half's first step, this lane, column k) in
-        // the table; the per-step offsets 4u fold into the ds_read immediate
-        const uint32_t base = 4u * (uint32_t)((kGroup * g + 16 * h - lane + 1) & (kTabRows - 1));
-        uint32_t addr[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k) addr[k] = base + bcode[k];
+        // word index of the row of the half's first step for this lane; the
+        // per-step offsets u fold into the ds_read immediate
+        const uint32_t base = (uint32_t)((kGroup * g + 16 * h - lane + 1) & (kTabRows - 1));
 
         // Narrow strips have too little work per step to hide the LDS latency
         // behind other waves, so the half's table reads are issued up front;
-        // wide strips read one step at a time.
+        // wide strips read one step at a time.  Each step reads one row word
+        // (the four substitution terms of the row's base); v_dot4 with the
+        // column's one-hot b-code picks its term and adds the diagonal.
         constexpr bool kHoist = (C <= 2);
-        int32_t kdh[kHoist ? 16 : 1][C];
+        uint32_t rwh[kHoist ? 16 : 1];
         if constexpr (kHoist) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-#pragma unroll
-                for (int k = 0; k < C; ++k) kdh[u][k] = (int32_t)lds8[addr[k] + 4 * u];
+            for (int u = 0; u < 16; ++u) rwh[u] = lds[base + u];
         }
 
 #pragma unroll
@@ -341,13 +341,13 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
             int32_t left = Lr;
             int32_t diag = Dg;
             int32_t tail = 0;  // the last column's previous value (+1 in the V domain)
+            uint32_t rw;
+            if constexpr (kHoist) rw = rwh[u];
+            else rw = lds[base + u];
 #pragma unroll
             for (int k = 0; k < C; ++k) {
-                int32_t kd;
-                if constexpr (kHoist) kd = kdh[u][k];
-                else kd = (int32_t)lds8[addr[k] + 4 * u];
                 const int32_t up = V[k];
-                const int32_t cD = diag + kd;
+                const int32_t cD = __builtin_amdgcn_sdot4((int)rw, (int)onehot[k], diag, false);
                 int32_t v;
                 if constexpr (DIRS) {
                     const int32_t cU = up + 1;
