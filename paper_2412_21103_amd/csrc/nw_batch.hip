@@ -22,7 +22,7 @@ constexpr int kBlockThreads = kWave * kWavesPerBlock;
 // latencies (all-pairs 83 -> 67 ms); sweeps with directions keep 2: more would
 // stretch each pair's wave, and the largest pairs already set the makespan.
 constexpr int blocks_per_cu(bool dirs) { return dirs ? 2 : 4; }
-constexpr int kBuckets = 64;
+constexpr int kBuckets = 512;
 
 struct KArgs {
     int32_t njobs, nseq;
@@ -116,9 +116,13 @@ __global__ void k_zero(int32_t* p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// 0..511, larger cost -> larger bucket: eight buckets per octave (by the three
+// bits below the leading one), so the queue runs within 1/8 octave of
+// largest-first
 __device__ __forceinline__ int cost_bucket(int64_t cost) {
-    // 0..63, larger cost -> larger bucket
-    return cost <= 0 ? 0 : 63 - __clzll((unsigned long long)cost);
+    if (cost < 8) return cost <= 0 ? 0 : (int)cost;
+    const int e = 63 - __clzll((unsigned long long)cost);
+    return 8 * e + (int)((cost >> (e - 3)) & 7);
 }
 
 template <bool ALLPAIRS>
@@ -426,7 +430,7 @@ struct Layout {
 // a launch uses as many slots as the workspace it is given holds (at least
 // one block's worth), so a smaller workspace only costs parallelism.
 constexpr size_t kSlotBudget = size_t(128) << 30;
-constexpr size_t kHeaderBytes = 1024;  // queue, hist[64], cursor[64]
+constexpr size_t kHeaderBytes = 5120;  // queue (0), hist[512] (1024), cursor[512] (3072)
 
 static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di,
                          size_t ws_limit = SIZE_MAX) {
@@ -517,8 +521,8 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.status = job.status;
     A.cells = job.cells;
     A.queue = (int32_t*)base;
-    A.hist = (int32_t*)(base + 64 * 4);
-    A.cursor = (int32_t*)(base + 128 * 4);
+    A.hist = (int32_t*)(base + 1024);
+    A.cursor = (int32_t*)(base + 3072);
     A.order = (int32_t*)(base + L.off_order);
     A.bnd = (int32_t*)(base + L.off_bnd);
     A.bnd_stride = L.bnd_stride;
@@ -528,7 +532,8 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.rev_stride = L.rev_stride;
 
     const unsigned pb = (unsigned)((job.njobs + 255) / 256);
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, (int32_t*)base, 256);
+    constexpr int kHeaderInts = (int)(kHeaderBytes / 4);
+    hipLaunchKernelGGL(k_zero, dim3((kHeaderInts + 255) / 256), dim3(256), 0, st, (int32_t*)base, kHeaderInts);
     if (job.allpairs) {
         hipLaunchKernelGGL(k_hist<true>, dim3(pb), dim3(256), 0, st, A);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor);

@@ -486,34 +486,89 @@ struct DirWindow {
     }
 };
 
-// Walk the stored directions of one pair from (m, n) back to (0, 0), one wave,
-// through a small LDS window of 4 groups x 16 lanes x C words anchored at the
-// current cell.  rev[q] gets the q-th move counted from the end.  Returns the
-// number of moves, or -1 if a stored tag is invalid.
+// Walk the stored directions of one pair from (m, n) back to (0, 0), one wave.
+// The walk is one dependent chain of lookups, so it runs on wave-uniform
+// scalar state and each move costs a few scalar operations and one
+// v_readlane:
+//  - the cell's strip s, lane l, column k and step t = i - r0(s) - 1 + l are
+//    kept up to date move by move, without divisions (tags 2 and 3 step up a
+//    row, tags 1 and 3 step left a column);
+//  - the direction words come from a window of 4 groups x 16 lanes x C words
+//    anchored at (group gw, lane lw) as its top-right corner and held flat in
+//    C VGPRs: word x = ((g-gw+3)*16 + l-lw+15)*C + k sits in lane x % 64 of
+//    register x / 64.  A move reads it from a copy of the current register,
+//    which changes only when x crosses a 64-word boundary.  The walk only
+//    moves up and left, so it leaves the window through its lowest group, its
+//    leftmost lane or into the previous strip; then the window is reloaded
+//    around the current cell;
+//  - moves collect one per lane in a VGPR and go out 64 bytes at a time.
+// The lane index is computed here, not shared with the fill: values derived
+// from it would otherwise be hoisted to the kernel's start and held in VGPRs
+// across the sweeps.  rev[q] gets the q-th move counted from the end.
+// Returns the number of moves, or -1 if a stored tag is invalid.
+//
+// For a band, strip s swept grid rows r0(s)+1 .. with r0(s) =
+// max(0, s*64*C - band_hi) and every strip has G groups of storage.
 template <int C>
 __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, int m, int n,
-                                             int groups_per_strip, uint32_t* lds,
+                                             int groups_per_strip, uint32_t* /*lds*/,
                                              uint8_t* __restrict__ rev, int band_hi = 1 << 30) {
-    const int lane = lane_id();
+    constexpr int kCols = kWave * C;
+    constexpr int kLogC = (C == 8) ? 3 : (C == 4) ? 2 : (C == 2) ? 1 : 0;
+    int lane;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lane));
+    const int G = groups_per_strip;
     int i = m, j = n;
     int64_t q = 0;
-    DirWindow<C> win(dirs, groups_per_strip, lds, band_hi);
+    uint32_t win[C];
+#pragma unroll
+    for (int r = 0; r < C; ++r) win[r] = 0;
+    uint32_t buf = 0;
     while (i > 0 && j > 0) {
-        const int tag = win.tag(i, j);
-        if (tag == 0) return -1;
-        const int mv = 4 - tag;
-        rev[q] = (uint8_t)mv;  // every lane stores the same byte
-        ++q;
-        if (mv == 1) {
-            --i;
-            --j;
-        } else if (mv == 2) {
-            --i;
-        } else {
-            --j;
+        const int col0 = j - 1;
+        const int s = col0 / kCols;
+        int l = (col0 - s * kCols) >> kLogC;
+        int k = (col0 - s * kCols) & (C - 1);
+        int t = i - max(0, s * kCols - band_hi) - 1 + l;
+        const int gw = t >> 4, lw = l;
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            const int x = kWave * r + lane;
+            const int gq = gw - 3 + (x >> (4 + kLogC));
+            const int lk = x & (16 * C - 1);
+            if (gq >= 0 && (lw - 15) * C + lk >= 0)
+                win[r] = dirs[((size_t)s * G + gq) * kCols + (lw - 15) * C + lk];
+        }
+        const int tmin = 16 * (gw - 3), lmin = max(lw - 15, 0);
+        const int xo = ((3 - gw) << (4 + kLogC)) + ((15 - lw) << kLogC);
+        int cur_r = -1;
+        uint32_t cur = 0;
+        for (;;) {
+            const int x = ((t >> 4) << (4 + kLogC)) + (l << kLogC) + k + xo;
+            if ((x >> 6) != cur_r) {
+                cur_r = x >> 6;
+                cur = win[0];
+#pragma unroll
+                for (int r = 1; r < C; ++r) cur = (cur_r == r) ? win[r] : cur;
+            }
+            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)cur, x & 63);
+            const int tag = (int)((word >> (2 * (t & 15))) & 3u);
+            if (__builtin_expect(tag == 0, 0)) return -1;
+            buf = (lane == (int)(q & 63)) ? (uint32_t)(4 - tag) : buf;
+            ++q;
+            if (__builtin_expect((q & 63) == 0, 0)) rev[q - 64 + lane] = (uint8_t)buf;
+            const int up = tag >> 1, left = tag & 1;
+            const int kk = k - left;
+            const int wrap = (int)((uint32_t)kk >> 31);
+            i -= up;
+            j -= left;
+            k = kk & (C - 1);
+            l -= wrap;
+            t -= up + wrap;
+            if ((i <= 0) | (j <= 0) | (t < tmin) | (l < lmin)) break;
         }
     }
-    // first column: vertical moves; first row: horizontal moves
+    if ((q & 63) != 0 && lane < (int)(q & 63)) rev[(q & ~(int64_t)63) + lane] = (uint8_t)buf;
     for (int x = lane; x < i; x += kWave) rev[q + x] = 2;
     q += i;
     for (int x = lane; x < j; x += kWave) rev[q + x] = 3;
