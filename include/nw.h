@@ -181,6 +181,36 @@ int nw_allpairs_scores(int32_t nseq, const uint8_t *pool, const int64_t *off,
                        void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Centre-star multiple alignment (paper Sec. 3.2, Multiple Alignment): the
+ * centre is the sequence whose scores against the other sequences sum
+ * highest in `scores` (device int32 nseq x nseq, as nw_allpairs_scores writes
+ * it; the diagonal is ignored; the lowest index wins ties).  Every other
+ * sequence is aligned to the centre (centre in the rows, the single-path
+ * traceback of nw_align), and the pairwise alignments are merged with the
+ * centre as the reference, keeping all their gaps: before each centre
+ * residue (and after the last) the alignment has as many columns as the
+ * longest insertion any sequence makes there, a row's inserted residues fill
+ * the first of those columns, and every column a row does not fill holds
+ * gap_byte (which should not occur in the sequences).
+ *
+ * Outputs (device): *center (int32), *width (int64: the alignment's width,
+ * or -1 if a pairwise alignment failed), and msa rows r = 0..nseq-1 (row r is
+ * sequence r, row stride width_cap bytes, first *width bytes of each row).
+ * The rows are written only if *width <= width_cap; the width never exceeds
+ * the sum of all lengths, so width_cap = sum(len) always suffices.  Sequence
+ * k = pool[off[k] .. off[k]+len[k]); max_len (host) bounds every len[k];
+ * nseq * max_len must stay below 2^31 (NW_ERANGE).  nseq = 0 writes nothing.
+ * The workspace holds the pairwise alignments and the batch engine's slots;
+ * the call is asynchronous on `stream` and not meant for graph capture.
+ * ------------------------------------------------------------------------ */
+int nw_center_star_workspace_size(int32_t nseq, int32_t max_len, size_t *bytes);
+
+int nw_center_star(int32_t nseq, const uint8_t *pool, const int64_t *off, const int32_t *len,
+                   int32_t max_len, nw_scoring sc, const int32_t *scores, uint8_t gap_byte,
+                   int32_t *center, uint8_t *msa, int64_t width_cap, int64_t *width, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Band model: a learned first half-width for the certified band.
  *
  * The paper closes (Sec. 5) by naming efficiency without missing an optimal

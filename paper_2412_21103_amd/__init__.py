@@ -97,6 +97,9 @@ def lib():
         L.nw_autotune.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp, _vp]
         L.nw_allpairs_workspace_size.argtypes = [_i32, _i32, ctypes.POINTER(_sz)]
         L.nw_allpairs_scores.argtypes = [_i32, _vp, _vp, _vp, _i32, Scoring, _vp, _vp, _sz, _vp]
+        L.nw_center_star_workspace_size.argtypes = [_i32, _i32, ctypes.POINTER(_sz)]
+        L.nw_center_star.argtypes = [_i32, _vp, _vp, _vp, _i32, Scoring, _vp, ctypes.c_uint8, _vp, _vp, _i64,
+                                     _vp, _vp, _sz, _vp]
         L.nw_release_caches.restype = None
         L.nw_profile_begin.restype = ctypes.c_int
         L.nw_profile_end.argtypes = [ctypes.POINTER(KernelTime), _i32, ctypes.POINTER(_i32)]
@@ -405,6 +408,36 @@ def autotune(pool, a_off, a_len, b_off, b_len, max_len: int, stream=None):
                              int(max_len), _ptr(scores), _ptr(paths), _ptr(path_off), _ptr(plen), _ptr(ws),
                              ws.numel(), costs, _stream(stream)), "nw_autotune")
     return {"dirs": list(costs[:3]), "score": list(costs[3:])}
+
+
+def center_star_workspace_size(nseq: int, max_len: int) -> int:
+    out = _sz(0)
+    _check(lib().nw_center_star_workspace_size(int(nseq), int(max_len), ctypes.byref(out)),
+           "nw_center_star_workspace_size")
+    return int(out.value)
+
+
+def center_star(pool: torch.Tensor, off: torch.Tensor, lens: torch.Tensor, max_len: int,
+                scores: torch.Tensor, scoring=PAPER_SCORING, gap_byte: int = 255, width_cap: int | None = None,
+                workspace: torch.Tensor | None = None, stream=None):
+    """Centre-star multiple alignment.  ``scores`` is the nseq x nseq matrix of
+    ``allpairs``.  Returns ``(center, msa, width)`` device tensors: int32[1],
+    uint8[nseq, width_cap] (row r = sequence r with gaps; the first ``width``
+    bytes of each row are the alignment) and int64[1].  ``width_cap``
+    defaults to the sum of the lengths, which always suffices."""
+    nseq = int(lens.numel())
+    dev = _dev()
+    if width_cap is None:
+        width_cap = max(int(lens.to(torch.int64).sum().item()), 1)
+    ws = _workspace(center_star_workspace_size(nseq, max_len), workspace)
+    center = torch.zeros(1, dtype=torch.int32, device=dev)
+    width = torch.zeros(1, dtype=torch.int64, device=dev)
+    msa = torch.empty((nseq, int(width_cap)), dtype=torch.uint8, device=dev)
+    st = lib().nw_center_star(nseq, _ptr(pool), _ptr(off), _ptr(lens), int(max_len), _sc(scoring), _ptr(scores),
+                              int(gap_byte), _ptr(center), _ptr(msa), int(width_cap), _ptr(width), _ptr(ws),
+                              ws.numel(), _stream(stream))
+    _check(st, "nw_center_star")
+    return center, msa, width
 
 
 def allpairs(pool: torch.Tensor, off: torch.Tensor, lens: torch.Tensor, max_len: int,

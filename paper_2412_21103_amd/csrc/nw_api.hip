@@ -716,4 +716,32 @@ int nw_allpairs_scores(int32_t nseq, const uint8_t* pool, const int64_t* off, co
     return launch_batch(J, ws, ws_bytes, (hipStream_t)stream, di);
 }
 
+// -------------------------------------------------------------- center star
+
+int nw_center_star_workspace_size(int32_t nseq, int32_t max_len, size_t* bytes) {
+    if (!bytes || nseq < 0 || max_len < 0) return NW_EINVAL;
+    if ((int64_t)nseq * std::max(max_len, 1) >= INT32_MAX) return NW_ERANGE;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    *bytes = center_star_workspace_bytes(nseq, std::max(max_len, 1), di);
+    return NW_OK;
+}
+
+int nw_center_star(int32_t nseq, const uint8_t* pool, const int64_t* off, const int32_t* len, int32_t max_len,
+                   nw_scoring sc, const int32_t* scores, uint8_t gap_byte, int32_t* center, uint8_t* msa,
+                   int64_t width_cap, int64_t* width, void* ws, size_t ws_bytes, void* stream) {
+    if (nseq < 0 || max_len < 0 || width_cap < 0) return NW_EINVAL;
+    if ((int64_t)nseq * std::max(max_len, 1) >= INT32_MAX) return NW_ERANGE;
+    int st = check_lengths(max_len, max_len, sc);
+    if (st) return st;
+    if ((st = check_scoring(sc, true))) return st;
+    if (nseq == 0) return NW_OK;
+    if (!pool || !off || !len || !scores || !center || !width || !ws || (width_cap > 0 && !msa)) return NW_EINVAL;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    return launch_center_star(nseq, pool, off, len, std::max(max_len, 1), sc, scores, gap_byte, center, msa,
+                              width_cap, width, ws, ws_bytes, (hipStream_t)stream, di);
+}
+
 }  // extern "C"

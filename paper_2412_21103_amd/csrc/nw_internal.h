@@ -87,6 +87,13 @@ size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const De
 int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t stream,
                  const DeviceInfo& di);
 
+// Center-star multiple alignment (nw_msa.hip).
+size_t center_star_workspace_bytes(int32_t nseq, int32_t max_len, const DeviceInfo& di);
+int launch_center_star(int32_t nseq, const uint8_t* pool, const int64_t* off, const int32_t* len, int32_t max_len,
+                       const nw_scoring& sc, const int32_t* scores, uint8_t gap, int32_t* center, uint8_t* msa,
+                       int64_t width_cap, int64_t* width, void* ws, size_t ws_bytes, hipStream_t st,
+                       const DeviceInfo& di);
+
 // Sweep-width cost table (per device), filled by nw_autotune.
 void set_step_costs(int device, const int32_t dirs[3], const int32_t score[3]);
 void reset_step_costs();
