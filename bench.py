@@ -290,12 +290,100 @@ def bench_allpairs(args):
     return common_fields(args, cells / (ms * 1e-3) / 1e9, ms, config, roof, cpu)
 
 
+def bench_center_star(args):
+    """Centre-star multiple alignment of the 512 all-pairs sequences: the
+    all-pairs score matrix, then the centre pick, the 511 alignments to the
+    centre with traceback and the merge, one pass per step."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_2412_21103_amd as nwp
+    from workloads import config_allpairs, pack_seqs
+
+    print("bench: generating the 512 sequences", file=sys.stderr, flush=True)
+    seqs = config_allpairs()
+    pool, off, lens = pack_seqs(seqs)
+    nseq = len(seqs)
+    max_len = int(lens.max())
+    l64 = lens.astype(np.int64)
+    cells_all = int((l64.sum() ** 2 - (l64 ** 2).sum()) // 2)
+    width_cap = int(l64.sum())
+    dev = torch.device("cuda", 0)
+    t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to(dev)
+    d = [t(pool, np.uint8), t(off, np.int64), t(lens, np.int32)]
+    S = torch.empty((nseq, nseq), dtype=torch.int32, device=dev)
+    center = torch.zeros(1, dtype=torch.int32, device=dev)
+    width = torch.zeros(1, dtype=torch.int64, device=dev)
+    msa = torch.empty((nseq, width_cap), dtype=torch.uint8, device=dev)
+    ws_a = nwp.allpairs_workspace_size(nseq, max_len)
+    ws_c = nwp.center_star_workspace_size(nseq, max_len)
+    ws = torch.empty(max(ws_a, ws_c), dtype=torch.uint8, device=dev)
+    L = nwp.lib()
+    sc = nwp.Scoring(*nwp.PAPER_SCORING)
+    stream = torch.cuda.current_stream()
+    vp = ctypes.c_void_p
+    ptr = lambda x: vp(x.data_ptr())
+
+    def step():
+        st = L.nw_allpairs_scores(nseq, *[ptr(x) for x in d], max_len, sc, ptr(S), ptr(ws), ws_a,
+                                  vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_allpairs_scores")
+        st = L.nw_center_star(nseq, *[ptr(x) for x in d], max_len, sc, ptr(S), 255, ptr(center), ptr(msa),
+                              width_cap, ptr(width), ptr(ws), ws_c, vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_center_star")
+
+    ms, prof = timed_steps(step, args, torch.cuda.synchronize)
+    c = int(center.item())
+    w = int(width.item())
+    cells_star = int(l64[c] * (l64.sum() - l64[c]))
+    cells = cells_all + cells_star
+    k = prof.get("nw_allpairs")
+    roof = alu_roofline("nw_allpairs", cells_all, k[1] / k[0] if k else None, 2)
+    phases = {name: round(v[1] / v[0], 4) for name, v in prof.items()
+              if name in ("nw_allpairs", "nw_msa_center", "nw_batch", "nw_msa_merge") and v[0]}
+    cpu = exact = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import msa as omsa
+        nt = oracle.max_threads()
+        ns = 48
+        sub = seqs[:ns]
+        sp, so, sl = pack_seqs(sub)
+        s64 = sl.astype(np.int64)
+        print(f"bench: CPU oracle centre star on the first {ns} sequences ({nt} threads)", file=sys.stderr,
+              flush=True)
+        c0 = time.perf_counter()
+        M_ref = oracle.allpairs(sp, so, sl, oracle.PAPER_SCORING)
+        c_ref, A_ref = omsa.center_star(sub, oracle.PAPER_SCORING, 255, scores=M_ref)
+        c1 = time.perf_counter()
+        sub_cells = int((s64.sum() ** 2 - (s64 ** 2).sum()) // 2 + s64[c_ref] * (s64.sum() - s64[c_ref]))
+        gd = [t(sp, np.uint8), t(so, np.int64), t(sl, np.int32)]
+        gS = nwp.allpairs(*gd, int(sl.max()), nwp.PAPER_SCORING)
+        gc, gM, gw = nwp.center_star(*gd, int(sl.max()), gS, nwp.PAPER_SCORING, gap_byte=255)
+        gw = int(gw.item())
+        exact = bool(int(gc.item()) == c_ref and gw == A_ref.shape[1]
+                     and np.array_equal(gM.cpu().numpy()[:, :gw], A_ref)
+                     and np.array_equal(gS.cpu().numpy(), M_ref))
+        cpu = {"value": round(sub_cells / (c1 - c0) / 1e9, 4), "unit": "GCUPS", "cores": nt, "kind": "oracle",
+               "sample": f"the first {ns} sequences ({sub_cells} cells): all-pairs scores (OpenMP over pairs), "
+                         f"the {ns - 1} alignments to the centre and the merge (one thread), "
+                         f"{round(c1 - c0, 2)} s"}
+    config = {"workload": f"center_star_{nseq}", "sequences": nseq, "cells": cells, "allpairs_cells": cells_all,
+              "alignment_cells": cells_star, "center": c, "width": w, "scoring": list(nwp.PAPER_SCORING),
+              "phase_ms": phases, "bit_exact_vs_oracle_sample": exact}
+    return common_fields(args, cells / (ms * 1e-3) / 1e9, ms, config, roof, cpu)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["long_pair", "batch", "allpairs"], default="long_pair")
+    ap.add_argument("--workload", choices=["long_pair", "batch", "allpairs", "center_star"], default="long_pair")
     ap.add_argument("--length", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-band", action="store_true", help="skip the learned-band batch")
@@ -322,6 +410,9 @@ def main():
         return 0
     if args.workload == "allpairs":
         print(json.dumps(bench_allpairs(args)), flush=True)
+        return 0
+    if args.workload == "center_star":
+        print(json.dumps(bench_center_star(args)), flush=True)
         return 0
 
     import ctypes

@@ -340,11 +340,14 @@ int launch_center_star(int32_t nseq, const uint8_t* pool, const int64_t* off, co
     int32_t* slot_col = ins + (ml + 1);
     int32_t* res_col = slot_col + (ml + 1);
 
-    hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, st, (int32_t*)base, (int64_t)64);
-    hipLaunchKernelGGL(k_zero32, dim3((unsigned)std::min<int64_t>(di.cus, (ml + 1 + 255) / 256)), dim3(256), 0, st,
-                       ins, ml + 1);
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((nseq + 255) / 256)), dim3(256), 0, st, nseq, scores, sums);
-    hipLaunchKernelGGL(k_argmax, dim3(1), dim3(1024), 0, st, nseq, sums, center, center_out);
+    {
+        ProfScope ps("nw_msa_center", st);
+        hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, st, (int32_t*)base, (int64_t)64);
+        hipLaunchKernelGGL(k_zero32, dim3((unsigned)std::min<int64_t>(di.cus, (ml + 1 + 255) / 256)), dim3(256), 0,
+                           st, ins, ml + 1);
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)((nseq + 255) / 256)), dim3(256), 0, st, nseq, scores, sums);
+        hipLaunchKernelGGL(k_argmax, dim3(1), dim3(1024), 0, st, nseq, sums, center, center_out);
+    }
     if (np > 0) {
         PairArgs P{nseq, off, len, center, L.path_stride, a_off, a_len, b_off, b_len, path_off, rowi};
         hipLaunchKernelGGL(k_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, P);
@@ -385,12 +388,16 @@ int launch_center_star(int32_t nseq, const uint8_t* pool, const int64_t* off, co
     A.width_cap = width_cap;
     A.gap = gap;
     A.nseq = nseq;
-    if (np > 0) hipLaunchKernelGGL(k_ins, dim3((unsigned)np), dim3(kWave), 0, st, A);
-    hipLaunchKernelGGL(k_cols, dim3(1), dim3(1024), 0, st, A);
-    hipLaunchKernelGGL(k_msa_fill, dim3((unsigned)std::min<int64_t>(4 * di.cus, std::max<int64_t>(1, nseq * ml / 256 + 1))),
-                       dim3(256), 0, st, A);
-    hipLaunchKernelGGL(k_msa_center, dim3((unsigned)std::min<int64_t>(di.cus, ml / 256 + 1)), dim3(256), 0, st, A);
-    if (np > 0) hipLaunchKernelGGL(k_msa_emit, dim3((unsigned)np), dim3(kWave), 0, st, A);
+    {
+        ProfScope ps("nw_msa_merge", st);
+        if (np > 0) hipLaunchKernelGGL(k_ins, dim3((unsigned)np), dim3(kWave), 0, st, A);
+        hipLaunchKernelGGL(k_cols, dim3(1), dim3(1024), 0, st, A);
+        hipLaunchKernelGGL(k_msa_fill,
+                           dim3((unsigned)std::min<int64_t>(4 * di.cus, std::max<int64_t>(1, nseq * ml / 256 + 1))),
+                           dim3(256), 0, st, A);
+        hipLaunchKernelGGL(k_msa_center, dim3((unsigned)std::min<int64_t>(di.cus, ml / 256 + 1)), dim3(256), 0, st, A);
+        if (np > 0) hipLaunchKernelGGL(k_msa_emit, dim3((unsigned)np), dim3(kWave), 0, st, A);
+    }
     return hipGetLastError() == hipSuccess ? NW_OK : NW_EDEVICE;
 }
 
