@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs * SIMDs * lanes * clock: 39.32 T lane-ops/s
-FILL_OPS_PER_CELL = 5  # diagonal add, vertical add, max3, tag clear, tag shift
+FILL_OPS_PER_CELL = 5  # diagonal term, vertical add, max3, tag clear, tag shift
 KERNEL_SOURCES = ["paper_2412_21103_amd/csrc/nw_common.h", "paper_2412_21103_amd/csrc/nw_strip.h",
                   "paper_2412_21103_amd/csrc/nw_single.hip"]
 COUNTERS = os.path.join(ROOT, "profiles", "fill_coop_long_pair_65536.counters.json")
@@ -394,7 +394,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(pairs are independent, see DESIGN.md for how the work would shard)", file=sys.stderr)
+              "(pairs are independent; several GPUs would each run a cost-balanced share of them)", file=sys.stderr)
         return 2
     if args.copy_probe > 0:
         import torch
