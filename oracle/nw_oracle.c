@@ -23,6 +23,9 @@
  *    3 horizontal.
  *  - Multiple alignment front end (Sec. 3.2, Eq. 2): all n(n-1)/2 pairwise
  *    scores of a sequence set, as a symmetric matrix.
+ *  - Co-optimal alignments (Sec. 2.4 keeps every optimal path): the number
+ *    of optimal paths of a pair, modulo 2^64 with a flag for counts of 2^64
+ *    and more.
  *
  * The traceback re-derives each move from H by re-evaluating the three
  * candidates (it stores no directions), except in the memory-saving mode,
@@ -316,4 +319,100 @@ int orc_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/*
+ * Co-optimal alignments (Sec. 2.4 keeps every path that reaches the optimal
+ * score).  N(i,j), the number of optimal paths from (0,0) to (i,j), follows
+ * the fill: N(0,0) = 1; a cell of the first row or column has one path;
+ * elsewhere N(i,j) is the sum of N over the neighbours whose candidate
+ * (H(i-1,j-1) + s, H(i-1,j) + g, H(i,j-1) + g) equals H(i,j).  Counts are
+ * kept modulo 2^64 together with a flag F(i,j) = [true count >= 2^64]: it is
+ * set when a summed neighbour has it set or when the sum wraps.
+ * Two rows of H, N and F.  Returns 0, or -1 if memory runs out.
+ */
+int orc_count(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+              int32_t match, int32_t mismatch, int32_t gap,
+              int32_t *score, uint64_t *count, uint8_t *saturated)
+{
+    int32_t *H0 = malloc((size_t)(n + 1) * sizeof(int32_t));
+    int32_t *H1 = malloc((size_t)(n + 1) * sizeof(int32_t));
+    uint64_t *N0 = malloc((size_t)(n + 1) * sizeof(uint64_t));
+    uint64_t *N1 = malloc((size_t)(n + 1) * sizeof(uint64_t));
+    uint8_t *F0 = malloc((size_t)(n + 1));
+    uint8_t *F1 = malloc((size_t)(n + 1));
+    if (!H0 || !H1 || !N0 || !N1 || !F0 || !F1) {
+        free(H0); free(H1); free(N0); free(N1); free(F0); free(F1);
+        return -1;
+    }
+    for (int64_t j = 0; j <= n; ++j) {
+        H0[j] = (int32_t)(j * gap);
+        N0[j] = 1;
+        F0[j] = 0;
+    }
+    for (int64_t i = 1; i <= m; ++i) {
+        H1[0] = (int32_t)(i * gap);
+        N1[0] = 1;
+        F1[0] = 0;
+        for (int64_t j = 1; j <= n; ++j) {
+            int32_t d = H0[j - 1] + subst(a[i - 1], b[j - 1], match, mismatch);
+            int32_t u = H0[j] + gap;
+            int32_t l = H1[j - 1] + gap;
+            int32_t h = max3i(d, u, l);
+            uint64_t s = 0;
+            uint8_t f = 0;
+            if (d == h) {
+                uint64_t t = s + N0[j - 1];
+                f |= (uint8_t)(F0[j - 1] | (t < s));
+                s = t;
+            }
+            if (u == h) {
+                uint64_t t = s + N0[j];
+                f |= (uint8_t)(F0[j] | (t < s));
+                s = t;
+            }
+            if (l == h) {
+                uint64_t t = s + N1[j - 1];
+                f |= (uint8_t)(F1[j - 1] | (t < s));
+                s = t;
+            }
+            H1[j] = h;
+            N1[j] = s;
+            F1[j] = f;
+        }
+        int32_t *th = H0; H0 = H1; H1 = th;
+        uint64_t *tn = N0; N0 = N1; N1 = tn;
+        uint8_t *tf = F0; F0 = F1; F1 = tf;
+    }
+    *score = H0[n];
+    *count = N0[n];
+    *saturated = F0[n];
+    free(H0); free(H1); free(N0); free(N1); free(F0); free(F1);
+    return 0;
+}
+
+/* orc_count over a batch of pairs, OpenMP across pairs.  Returns -1 if any
+ * pair ran out of memory, else 0. */
+int orc_count_batch(int32_t npairs, const uint8_t *pool,
+                    const int64_t *a_off, const int32_t *a_len,
+                    const int64_t *b_off, const int32_t *b_len,
+                    int32_t match, int32_t mismatch, int32_t gap,
+                    int32_t *scores, uint64_t *counts, uint8_t *saturated, int32_t nthreads)
+{
+    int64_t *ord = order_by_cost(npairs, a_len, b_len);
+    int64_t fail = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : fail)
+    for (int64_t q = 0; q < npairs; ++q) {
+        int64_t k = ord[q];
+        if (orc_count(pool + a_off[k], a_len[k], pool + b_off[k], b_len[k], match, mismatch, gap,
+                      &scores[k], &counts[k], &saturated[k]) < 0)
+            fail += 1;
+    }
+    free(ord);
+    return fail ? -1 : 0;
 }

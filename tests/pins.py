@@ -126,3 +126,15 @@ def score_from_edit_distance(a, b, scoring):
     total = match * (len(a) + len(b)) - dist
     assert total % 2 == 0
     return total // 2
+
+
+def brute_force_all(a, b, scoring=(1, -1, -1)):
+    """Every optimal alignment, by exhaustive enumeration, in decreasing order
+    of the reversed move string under D > U > L."""
+    a = list(a)
+    b = list(b)
+    scored = [(path_score(p, a, b, scoring), p) for p in all_paths(len(a), len(b))]
+    best = max(s for s, _ in scored)
+    opt = [p for s, p in scored if s == best]
+    opt.sort(key=lambda p: tuple(_RANK[x] for x in reversed(p)), reverse=True)
+    return best, opt
