@@ -211,6 +211,43 @@ int nw_center_star(int32_t nseq, const uint8_t *pool, const int64_t *off, const 
                    size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Co-optimal alignments (Sec. 2.4: backtracking keeps every path that
+ * reaches the optimal score).
+ *
+ * For pair k (a = pool[a_off[k] ..+a_len[k]) in the rows, b = pool[b_off[k]
+ * ..+b_len[k]) in the columns, all device arrays as in nw_align_batch):
+ *   scores[k]    (int32)  H(m,n);
+ *   counts[k]    (uint64) the number of optimal paths modulo 2^64;
+ *   saturated[k] (uint8)  1 if that number is 2^64 or more, else 0.
+ * The number follows the fill: one path to every cell of the first row and
+ * column, elsewhere the sum over the neighbours whose candidate equals the
+ * cell's score.
+ *
+ * With k > 0 the call also lists the first min(k, count) optimal paths in the
+ * order of a depth-first search from (m,n) that tries the diagonal, then the
+ * vertical, then the horizontal move at each cell; path 0 is nw_align_batch's
+ * path.  Path r of pair q goes to paths[path_off[q] + r*(a_len[q]+b_len[q])
+ * ..] (moves 1/2/3 from (0,0) to (m,n), caller-computed int64 path_off with
+ * room for k*(a_len+b_len) bytes), its length to path_len[q*k + r] (int32),
+ * and the number listed to n_paths[q] (int32).  With k = 0, paths, path_off,
+ * path_len and n_paths may be NULL.  npairs*k must fit in int32 (NW_ERANGE).
+ *
+ * A pair longer than max_len is skipped: scores = INT32_MIN, counts 0,
+ * saturated 0, n_paths 0.  The workspace (caller-owned device memory) holds
+ * the job order and one slot per resident wave: the boundary column, and
+ * with k > 0 the tie bits of a whole pair (half a byte per cell) and the
+ * walk's state.  Smaller workspaces run fewer waves, down to one block of
+ * slots (NW_ENOSPC below that).  Asynchronous on `stream`.
+ * ------------------------------------------------------------------------ */
+int nw_cooptimal_workspace_size(int32_t npairs, int32_t max_len, int32_t k, size_t *bytes);
+
+int nw_cooptimal(int32_t npairs, const uint8_t *pool, const int64_t *a_off, const int32_t *a_len,
+                 const int64_t *b_off, const int32_t *b_len, int32_t max_len, nw_scoring sc,
+                 int32_t *scores, uint64_t *counts, uint8_t *saturated, int32_t k, uint8_t *paths,
+                 const int64_t *path_off, int32_t *path_len, int32_t *n_paths, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Band model: a learned first half-width for the certified band.
  *
  * The paper closes (Sec. 5) by naming efficiency without missing an optimal

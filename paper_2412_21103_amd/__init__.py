@@ -100,6 +100,9 @@ def lib():
         L.nw_center_star_workspace_size.argtypes = [_i32, _i32, ctypes.POINTER(_sz)]
         L.nw_center_star.argtypes = [_i32, _vp, _vp, _vp, _i32, Scoring, _vp, ctypes.c_uint8, _vp, _vp, _i64,
                                      _vp, _vp, _sz, _vp]
+        L.nw_cooptimal_workspace_size.argtypes = [_i32, _i32, _i32, ctypes.POINTER(_sz)]
+        L.nw_cooptimal.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _vp, _vp, _vp, _i32, _vp, _vp,
+                                   _vp, _vp, _vp, _sz, _vp]
         L.nw_release_caches.restype = None
         L.nw_profile_begin.restype = ctypes.c_int
         L.nw_profile_end.argtypes = [ctypes.POINTER(KernelTime), _i32, ctypes.POINTER(_i32)]
@@ -438,6 +441,42 @@ def center_star(pool: torch.Tensor, off: torch.Tensor, lens: torch.Tensor, max_l
                               ws.numel(), _stream(stream))
     _check(st, "nw_center_star")
     return center, msa, width
+
+
+def cooptimal_workspace_size(npairs: int, max_len: int, k: int = 0) -> int:
+    out = _sz(0)
+    _check(lib().nw_cooptimal_workspace_size(int(npairs), int(max_len), int(k), ctypes.byref(out)),
+           "nw_cooptimal_workspace_size")
+    return int(out.value)
+
+
+def cooptimal(pool: torch.Tensor, a_off: torch.Tensor, a_len: torch.Tensor, b_off: torch.Tensor,
+              b_len: torch.Tensor, max_len: int, scoring=PAPER_SCORING, k: int = 0,
+              workspace: torch.Tensor | None = None, stream=None):
+    """Co-optimal alignments of many pairs.  Returns ``(scores, counts, saturated)``
+    (int32, int64 holding the count modulo 2^64 bit for bit, uint8) and, with
+    ``k > 0``, also ``(paths, path_off, path_len, n_paths)``: pair q's path r
+    is ``paths[path_off[q] + r*(a_len[q]+b_len[q]) :][:path_len[q, r]]``."""
+    npairs = int(a_len.numel())
+    dev = _dev()
+    ws = _workspace(cooptimal_workspace_size(npairs, max_len, k), workspace)
+    scores = torch.empty(npairs, dtype=torch.int32, device=dev)
+    counts = torch.empty(npairs, dtype=torch.int64, device=dev)
+    sat = torch.empty(npairs, dtype=torch.uint8, device=dev)
+    paths = path_off = path_len = n_paths = None
+    if k > 0:
+        caps = (a_len.to(torch.int64) + b_len.to(torch.int64)) * k
+        path_off = torch.cumsum(caps, 0) - caps
+        paths = torch.empty(max(int(caps.sum().item()), 1), dtype=torch.uint8, device=dev)
+        path_len = torch.zeros((npairs, k), dtype=torch.int32, device=dev)
+        n_paths = torch.empty(npairs, dtype=torch.int32, device=dev)
+    st = lib().nw_cooptimal(npairs, _ptr(pool), _ptr(a_off), _ptr(a_len), _ptr(b_off), _ptr(b_len), int(max_len),
+                            _sc(scoring), _ptr(scores), _ptr(counts), _ptr(sat), int(k), _ptr(paths),
+                            _ptr(path_off), _ptr(path_len), _ptr(n_paths), _ptr(ws), ws.numel(), _stream(stream))
+    _check(st, "nw_cooptimal")
+    if k > 0:
+        return scores, counts, sat, paths, path_off, path_len, n_paths
+    return scores, counts, sat
 
 
 def allpairs(pool: torch.Tensor, off: torch.Tensor, lens: torch.Tensor, max_len: int,

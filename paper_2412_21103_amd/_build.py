@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnw.so")
-SOURCES = ["nw_api.hip", "nw_batch.hip", "nw_single.hip", "nw_mlp.hip", "nw_msa.hip"]
+SOURCES = ["nw_api.hip", "nw_batch.hip", "nw_single.hip", "nw_mlp.hip", "nw_msa.hip", "nw_coopt.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -744,4 +744,31 @@ int nw_center_star(int32_t nseq, const uint8_t* pool, const int64_t* off, const 
                               width_cap, width, ws, ws_bytes, (hipStream_t)stream, di);
 }
 
+int nw_cooptimal_workspace_size(int32_t npairs, int32_t max_len, int32_t k, size_t* bytes) {
+    if (!bytes || npairs < 0 || max_len < 0 || k < 0) return NW_EINVAL;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    *bytes = cooptimal_workspace_bytes(npairs, std::max(max_len, 1), k, di);
+    return NW_OK;
+}
+
+int nw_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
+                 const int64_t* b_off, const int32_t* b_len, int32_t max_len, nw_scoring sc, int32_t* scores,
+                 uint64_t* counts, uint8_t* saturated, int32_t k, uint8_t* paths, const int64_t* path_off,
+                 int32_t* path_len, int32_t* n_paths, void* ws, size_t ws_bytes, void* stream) {
+    if (npairs < 0 || max_len < 0 || k < 0) return NW_EINVAL;
+    if ((int64_t)npairs * k > INT32_MAX) return NW_ERANGE;
+    int st = check_lengths(max_len, max_len, sc);
+    if (st) return st;
+    if ((st = check_scoring(sc, false))) return st;
+    if (npairs == 0) return NW_OK;
+    if (!pool || !a_off || !a_len || !b_off || !b_len || !scores || !counts || !saturated || !ws) return NW_EINVAL;
+    if (k > 0 && (!paths || !path_off || !path_len || !n_paths)) return NW_EINVAL;
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    return launch_cooptimal(npairs, pool, a_off, a_len, b_off, b_len, std::max(max_len, 1), sc, scores, counts,
+                            saturated, k, paths, path_off, path_len, n_paths, ws, ws_bytes, (hipStream_t)stream, di);
+}
+
 }  // extern "C"

@@ -1,0 +1,510 @@
+// Co-optimal alignments (Sec. 2.4 keeps every path that reaches the optimal
+// score): per pair, the number N of optimal paths, kept modulo 2^64 with a
+// flag for N >= 2^64, and optionally the first k of those paths in the order
+// a depth-first search from (m,n) meets them when it tries the diagonal, then
+// the vertical, then the horizontal move at every cell (the first one is the
+// single tie-broken path of nw_align_batch).
+//
+// Fill.  One wave per pair from a persistent largest-first queue.  Lane l
+// holds columns j0+2l+1 and j0+2l+2 of a 128-column strip and sweeps the rows
+// on a skewed front (lane l is at row t+1-l at step t).  Per cell it keeps
+//     W = H - gap*(i+j)   (Eq. 1 becomes W = max(Wd + s - 2gap, Wu, Wl)),
+//     N mod 2^64 and F = [N >= 2^64],
+// and N is the sum of N over the neighbours whose candidate equals the
+// maximum, F the OR of theirs and of a wrapped sum.  The left neighbour's
+// values come by DPP from lane l-1; lane 0 reads the previous strip's last
+// column, which lane 63 wrote to a per-wave boundary buffer one row per step.
+// With k > 0 the three tie bits of every cell are packed 8 per step into a
+// 32-bit word per lane every 4 steps.
+//
+// Enumeration.  The same wave then walks: path 0 takes the first optimal move
+// at every cell from (m,n); each later path goes back to the deepest cell of
+// the previous one that still has an untried optimal move, takes the next
+// one, and again the first moves from there.  Every cell reached this way
+// has an optimal move (or is the origin), so no walk dead-ends.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "nw_common.h"
+#include "nw_internal.h"
+
+namespace nw {
+
+namespace {
+
+constexpr int kCoCols = 2;                       // columns per lane
+constexpr int kCoStrip = kWave * kCoCols;        // columns per strip
+constexpr int kCoWaves = 4;                      // waves per block
+constexpr int kCoBlocksPerCu = 4;
+constexpr int kCoBuckets = 512;                  // 8 cost buckets per octave
+constexpr size_t kCoHeader = 8192;               // hist[512], cursor[512] and next_job (ints)
+constexpr int kMoveD = 1, kMoveU = 2, kMoveL = 3;
+
+struct CoArgs {
+    int32_t npairs;
+    const uint8_t* pool;
+    const int64_t* a_off;
+    const int32_t* a_len;
+    const int64_t* b_off;
+    const int32_t* b_len;
+    int32_t max_len;
+    int32_t kdm, kdx;  // s - 2*gap for a match and a mismatch
+    int32_t gap;
+    int32_t* scores;
+    uint64_t* counts;
+    uint8_t* saturated;
+    int32_t k;
+    uint8_t* paths;
+    const int64_t* path_off;
+    int32_t* path_len;
+    int32_t* n_paths;
+    int32_t* hist;
+    int32_t* cursor;
+    int32_t* next_job;
+    int32_t* order;
+    uint8_t* slots;
+    int64_t slot_bytes;
+    int64_t off_tie;   // within a slot
+    int64_t off_walk;  // within a slot
+};
+
+__device__ __forceinline__ int cost_bucket(int64_t cost) {
+    if (cost < 8) return (int)max<int64_t>(cost, 0);
+    const int e = 63 - __builtin_clzll((unsigned long long)cost);
+    return 8 * e + (int)((cost >> (e - 3)) & 7);
+}
+
+__device__ __forceinline__ bool pair_ok(const CoArgs& A, int p) {
+    const int32_t m = A.a_len[p], n = A.b_len[p];
+    return m >= 0 && n >= 0 && m <= A.max_len && n <= A.max_len;
+}
+
+__global__ void k_co_zero(int32_t* p, int32_t n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_co_hist(CoArgs A) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.npairs) return;
+    const int b = pair_ok(A, p) ? cost_bucket((int64_t)A.a_len[p] * A.b_len[p]) : 0;
+    atomicAdd(&A.hist[b], 1);
+}
+
+// One block of kCoBuckets threads: cursor[b] = number of pairs in buckets
+// above b (largest first).
+__global__ __launch_bounds__(kCoBuckets) void k_co_scan(CoArgs A) {
+    __shared__ int32_t s[kCoBuckets];
+    const int t = threadIdx.x;
+    s[t] = A.hist[kCoBuckets - 1 - t];  // reversed: bucket 511 first
+    __syncthreads();
+    for (int d = 1; d < kCoBuckets; d <<= 1) {
+        const int32_t y = t >= d ? s[t - d] : 0;
+        __syncthreads();
+        s[t] += y;
+        __syncthreads();
+    }
+    const int b = kCoBuckets - 1 - t;
+    A.cursor[b] = s[t] - A.hist[b];
+}
+
+__global__ void k_co_scatter(CoArgs A) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.npairs) return;
+    const int b = pair_ok(A, p) ? cost_bucket((int64_t)A.a_len[p] * A.b_len[p]) : 0;
+    A.order[atomicAdd(&A.cursor[b], 1)] = p;
+}
+
+// One cell: the maximum of the three candidates, and the sum of the counts
+// of those equal to it.  Returns the tie bits (1 diagonal, 2 vertical,
+// 4 horizontal).  EXACT also keeps F, the OR of the summed neighbours' flags
+// and of a wrapped sum.  Without EXACT the caller only watches whether a
+// count reaches 2^62: while none does, no sum of three counts can wrap and
+// every F is 0; otherwise it recomputes the pair with EXACT.
+template <bool EXACT>
+__device__ __forceinline__ uint32_t cell(int32_t cd, int32_t wu, int32_t wl, uint64_t nd, uint64_t nu, uint64_t nl,
+                                         uint32_t fd, uint32_t fu, uint32_t fl, int32_t& w, uint64_t& n,
+                                         uint32_t& f) {
+    const int32_t h = imax3(cd, wu, wl);
+    const bool eD = cd == h, eU = wu == h, eL = wl == h;
+    if (EXACT) {
+        uint64_t s = eD ? nd : 0;
+        uint64_t t;
+        const bool o1 = __builtin_add_overflow(s, eU ? nu : 0, &t);
+        const bool o2 = __builtin_add_overflow(t, eL ? nl : 0, &s);
+        f = max(max(eD ? fd : 0u, eU ? fu : 0u), max(eL ? fl : 0u, (uint32_t)(o1 | o2)));
+        n = s;
+    } else {
+        n = (eD ? nd : 0) + (eU ? nu : 0) + (eL ? nl : 0);
+    }
+    w = h;
+    return (eD ? 1u : 0u) | (eU ? 2u : 0u) | (eL ? 4u : 0u);
+}
+
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+__device__ __forceinline__ uint64_t mk64(uint32_t l, uint32_t h) { return ((uint64_t)h << 32) | l; }
+
+// A boundary cell handed from one strip to the next: W, N (low, high), F.
+struct BCell {
+    int32_t w;
+    uint32_t nl, nh, f;
+};
+
+// Per-wave LDS: the row words of the 128 rows around the front (rows T-63 ..
+// T+64 for the block of 64 steps starting at T) and the previous strip's
+// column for rows T+1 .. T+64.
+struct WaveLds {
+    uint32_t rw[2 * kWave];
+    BCell col[kWave];
+};
+
+// Tie bits of cell (i,j), 1 <= i <= m, 1 <= j <= n, from the packed words of
+// the fill (strip s, group g of 4 steps, lane l).
+__device__ __forceinline__ uint32_t tie_bits(const uint32_t* tie, int64_t groups, int32_t i, int32_t j) {
+    const int32_t c = j - 1;
+    const int32_t s = c / kCoStrip, w = c % kCoStrip, l = w >> 1, kk = w & 1;
+    const int32_t t = i - 1 + l;
+    const uint32_t word = load_coherent_u32(tie + ((int64_t)s * groups + (t >> 2)) * kWave + l);
+    return (word >> (8 * (t & 3) + 4 * kk)) & 7u;
+}
+
+// The fill of one pair (m, n >= 1).  Returns, without EXACT, whether a
+// count reached 2^62 (then the caller recomputes with EXACT); the lane that
+// holds column n leaves its row-m values in w_end, n_end, f_end.
+template <bool ENUM, bool EXACT>
+__device__ bool fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int32_t m, int32_t n,
+                          int32_t& w_end, uint64_t& n_end, uint32_t& f_end) {
+    const int lane = lane_id();
+    const uint8_t* a = A.pool + A.a_off[p];
+    const uint8_t* b = A.pool + A.b_off[p];
+    BCell* bnd = (BCell*)slot;  // two buffers of max_len+1 rows
+    const int64_t bstride = (int64_t)A.max_len + 1;
+    uint32_t* tie = (uint32_t*)(slot + A.off_tie);
+    const int32_t steps = m + kWave - 1;
+    const int64_t groups = ((int64_t)steps + 3) / 4;
+    const int nstrips = (n + kCoStrip - 1) / kCoStrip;
+    uint32_t hiacc = 0;  // OR of the high words of every count
+    for (int s = 0; s < nstrips; ++s) {
+        const int j0 = s * kCoStrip;
+        const BCell* bin = bnd + (s & 1) * bstride;
+        BCell* bout = bnd + ((s & 1) ^ 1) * bstride;
+        const int32_t c0 = j0 + 2 * lane + 1, c1 = c0 + 1;
+        const uint32_t oh0 = 1u << (8 * (c0 <= n ? (b[c0 - 1] & 3) : 0));
+        const uint32_t oh1 = 1u << (8 * (c1 <= n ? (b[c1 - 1] & 3) : 0));
+        // lanes past column n stay at row 0; rows run 1..m for the others
+        const uint32_t rows = c0 <= n ? (uint32_t)m : 0u;
+        const bool hand = lane == kWave - 1 && s + 1 < nstrips;
+        // row 0: W = 0, N = 1, F = 0 everywhere (one path along the first row)
+        int32_t w0 = 0, w1 = 0;
+        uint64_t n0 = 1, n1 = 1;
+        uint32_t f0 = 0, f1 = 0;
+        int32_t dw = 0;  // diagonal input of column 0: the last step's left input
+        uint64_t dn = 1;
+        uint32_t df = 0;
+        uint32_t tw = 0;
+        fence_agent();  // the previous strip's column (written by lane 63) is visible
+        for (int32_t T = 0; T < steps; T += kWave) {
+            {
+                const int32_t r = T + 1 + lane;
+                const uint32_t older = T == 0 ? 0u : S.rw[kWave + lane];
+                const uint32_t word = r <= m ? row_word(a[r - 1] & 3u, A.kdm, A.kdx) : 0u;
+                BCell c{0, 1u, 0u, 0u};
+                if (s > 0 && r <= m) c = bin[r];
+                __builtin_amdgcn_wave_barrier();
+                S.rw[lane] = older;
+                S.rw[kWave + lane] = word;
+                S.col[lane] = c;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+            const int32_t cnt = min(kWave, steps - T);
+            // one step: lane l at row T+u+1-l
+            auto step = [&](int32_t u) {
+                const int32_t t = T + u;
+                const uint32_t rm1 = (uint32_t)(t - lane);  // row - 1
+                const int32_t rw = (int32_t)S.rw[kWave + u - lane];
+                const BCell in = S.col[u];
+                const int32_t lw = dpp_from_left(in.w, w1);
+                const uint32_t lnl = (uint32_t)dpp_from_left((int32_t)in.nl, (int32_t)lo32(n1));
+                const uint32_t lnh = (uint32_t)dpp_from_left((int32_t)in.nh, (int32_t)hi32(n1));
+                const uint32_t lf = EXACT ? (uint32_t)dpp_from_left((int32_t)in.f, (int32_t)f1) : 0u;
+                const uint64_t ln = mk64(lnl, lnh);
+                uint32_t bits = 0;
+                if (rm1 < rows) {
+                    int32_t nw0, nw1;
+                    uint64_t nn0, nn1;
+                    uint32_t nf0 = 0, nf1 = 0;
+                    const int32_t cd0 = __builtin_amdgcn_sdot4(rw, (int32_t)oh0, dw, false);
+                    const uint32_t b0 = cell<EXACT>(cd0, w0, lw, dn, n0, ln, df, f0, lf, nw0, nn0, nf0);
+                    const int32_t cd1 = __builtin_amdgcn_sdot4(rw, (int32_t)oh1, w0, false);
+                    const uint32_t b1 = cell<EXACT>(cd1, w1, nw0, n0, n1, nn0, f0, f1, nf0, nw1, nn1, nf1);
+                    w0 = nw0;
+                    n0 = nn0;
+                    w1 = nw1;
+                    n1 = nn1;
+                    if (EXACT) {
+                        f0 = nf0;
+                        f1 = nf1;
+                    } else {
+                        hiacc |= hi32(nn0) | hi32(nn1);
+                    }
+                    bits = b0 | (b1 << 4);
+                    // lane 63 hands its second column to the next strip
+                    if (hand) bout[rm1 + 1] = BCell{w1, lo32(n1), hi32(n1), f1};
+                }
+                dw = lw;
+                dn = ln;
+                df = lf;
+                if (ENUM) {
+                    tw = (tw >> 8) | (bits << 24);
+                    if ((t & 3) == 3 || t == steps - 1) {
+                        const uint32_t sh = (uint32_t)(8 * (3 - (t & 3)));
+                        tie[((int64_t)s * groups + (t >> 2)) * kWave + lane] = tw >> sh;
+                    }
+                }
+            };
+            int32_t u = 0;
+            for (; u + 1 < cnt; u += 2) {
+                step(u);
+                step(u + 1);
+            }
+            if (u < cnt) step(u);
+        }
+        if (s + 1 == nstrips) {
+            // lanes stop at row m, so the lane holding column n has H(m,n)
+            if (c0 == n) {
+                w_end = w0;
+                n_end = n0;
+                f_end = f0;
+            } else if (c1 == n) {
+                w_end = w1;
+                n_end = n1;
+                f_end = f1;
+            }
+        }
+        fence_agent();
+    }
+    return (hiacc >> 30) != 0;
+}
+
+// Scalar walk state: moves, remaining options and the cell before each move.
+struct Walk {
+    uint8_t* mv;
+    uint8_t* alt;
+    int32_t* ci;
+    int32_t* cj;
+};
+
+__device__ __forceinline__ uint32_t options(const uint32_t* tie, int64_t groups, int32_t i, int32_t j) {
+    if (i == 0) return 4u;
+    if (j == 0) return 2u;
+    return tie_bits(tie, groups, i, j);
+}
+
+// From cell (i,j) at depth d, always the first optimal move, to the origin.
+// All lanes run it with the same values and store the same bytes (no
+// lane-only branch inside the loop).  Returns the depth.
+__device__ int32_t descend(const uint32_t* tie, int64_t groups, const Walk& W, int32_t i, int32_t j, int32_t d) {
+    while (i > 0 || j > 0) {
+        const uint32_t o = uniform((int32_t)options(tie, groups, i, j));
+        const uint32_t bit = o & (0u - o);  // lowest set bit: D, then U, then L
+        const int mv = bit == 1u ? kMoveD : (bit == 2u ? kMoveU : kMoveL);
+        W.mv[d] = (uint8_t)mv;
+        W.alt[d] = (uint8_t)(o & ~bit);
+        W.ci[d] = i;
+        W.cj[d] = j;
+        if (mv != kMoveL) --i;
+        if (mv != kMoveU) --j;
+        ++d;
+    }
+    return d;
+}
+
+__device__ void emit_path(const CoArgs& A, const Walk& W, int p, int r, int32_t m, int32_t n, int32_t len) {
+    fence_agent();
+    uint8_t* out = A.paths + A.path_off[p] + (int64_t)r * (m + n);
+    for (int32_t x = lane_id(); x < len; x += kWave)
+        out[x] = (uint8_t)__hip_atomic_load(W.mv + (len - 1 - x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    A.path_len[(int64_t)p * A.k + r] = len;  // every lane, same value
+}
+
+// The job loop keeps every lane active on every path: the queue ticket comes
+// from an atomic that all lanes execute (lane 0 adds 1, the others 0), and
+// every lane stores the same outputs.  A lane-only branch near a back edge
+// would let the compiler split the loop per lane, and readfirstlane would
+// then stop reading lane 0.
+template <bool ENUM>
+__global__ __launch_bounds__(kWave * kCoWaves, kCoBlocksPerCu) void k_count(CoArgs A) {
+    __shared__ WaveLds lds[kCoWaves];
+    const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
+    const int64_t wave = (int64_t)blockIdx.x * kCoWaves + wv;
+    uint8_t* slot = A.slots + wave * A.slot_bytes;
+    for (;;) {
+        const int job = uniform(atomicAdd(A.next_job, lane == 0 ? 1 : 0));
+        if (job >= A.npairs) break;
+        const int p = uniform(A.order[job]);
+        const int32_t m = uniform(A.a_len[p]), n = uniform(A.b_len[p]);
+        const bool ok = m >= 0 && n >= 0 && m <= A.max_len && n <= A.max_len;
+        int32_t score = INT32_MIN;
+        uint64_t count = 0;
+        uint32_t flag = 0;
+        int32_t got = 0;
+        if (ok) {
+            int32_t w_end = 0;
+            uint64_t n_end = 1;
+            uint32_t f_end = 0;
+            if (m > 0 && n > 0) {
+                const bool wrapped = fill_pair<ENUM, false>(A, slot, lds[wv], p, m, n, w_end, n_end, f_end);
+                if (__ballot(wrapped)) fill_pair<false, true>(A, slot, lds[wv], p, m, n, w_end, n_end, f_end);
+                // the lane that holds column n at row m has the result
+                const int src = ((n - 1) % kCoStrip) / kCoCols;
+                w_end = __shfl(w_end, src);
+                n_end = mk64((uint32_t)__shfl((int32_t)lo32(n_end), src),
+                             (uint32_t)__shfl((int32_t)hi32(n_end), src));
+                f_end = (uint32_t)__shfl((int32_t)f_end, src);
+            }
+            score = w_end + A.gap * (m + n);
+            count = n_end;
+            flag = f_end != 0 ? 1u : 0u;
+            if (ENUM && A.k > 0) {
+                const int64_t groups = ((int64_t)m + kWave - 1 + 3) / 4;
+                const uint32_t* tie = (const uint32_t*)(slot + A.off_tie);
+                const int32_t L = m + n + 1;
+                Walk W{slot + A.off_walk, slot + A.off_walk + L, nullptr, nullptr};
+                W.ci = (int32_t*)(slot + A.off_walk + ((2 * (int64_t)L + 15) & ~(int64_t)15));
+                W.cj = W.ci + L;
+                fence_agent();
+                int32_t d = descend(tie, groups, W, m, n, 0);
+                emit_path(A, W, p, 0, m, n, d);
+                got = 1;
+                while (got < A.k) {
+                    fence_agent();
+                    // deepest position with an untried move, 64 positions at a time
+                    int32_t q = -1;
+                    for (int32_t hi = d - 1; hi >= 0 && q < 0; hi -= kWave) {
+                        const int32_t x = hi - lane;
+                        const bool has = x >= 0 && __hip_atomic_load(W.alt + x, __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT) != 0;
+                        const uint64_t ball = __ballot(has);
+                        if (ball) q = hi - (int32_t)__builtin_ctzll(ball);
+                    }
+                    if (q < 0) break;
+                    const int32_t i = uniform(__hip_atomic_load(W.ci + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    const int32_t j = uniform(__hip_atomic_load(W.cj + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    const uint32_t o = (uint32_t)uniform(
+                        (int32_t)__hip_atomic_load(W.alt + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    const uint32_t bit = o & (0u - o);
+                    const int mv = bit == 1u ? kMoveD : (bit == 2u ? kMoveU : kMoveL);
+                    fence_agent();  // every lane has read alt[q] before any lane rewrites it
+                    W.mv[q] = (uint8_t)mv;
+                    W.alt[q] = (uint8_t)(o & ~bit);
+                    d = descend(tie, groups, W, i - (mv != kMoveL ? 1 : 0), j - (mv != kMoveU ? 1 : 0), q + 1);
+                    emit_path(A, W, p, got, m, n, d);
+                    ++got;
+                }
+            }
+        }
+        // every lane, the same values
+        A.scores[p] = score;
+        A.counts[p] = count;
+        A.saturated[p] = (uint8_t)flag;
+        if (ENUM) A.n_paths[p] = got;
+    }
+}
+
+struct CoLayout {
+    int64_t slot_bytes, off_tie, off_walk;
+    size_t off_order, off_slots;
+    int64_t full_slots;
+};
+
+CoLayout co_layout(int32_t npairs, int32_t max_len, int32_t k, const DeviceInfo& di) {
+    CoLayout L{};
+    const int64_t ml = std::max(max_len, 1);
+    int64_t off = (int64_t)align_up((size_t)(2 * (ml + 1)) * sizeof(BCell), 256);  // boundary: 2 buffers
+    L.off_tie = off;
+    if (k > 0) {
+        const int64_t strips = (ml + kCoStrip - 1) / kCoStrip;
+        const int64_t groups = (ml + kWave - 1 + 3) / 4;
+        off += (int64_t)align_up((size_t)(strips * groups * kWave * 4), 256);
+        L.off_walk = off;
+        const int64_t Lw = 2 * ml + 1;
+        off += (int64_t)align_up(align_up(2 * (size_t)Lw, 16) + 8 * (size_t)Lw, 256);
+    } else {
+        L.off_walk = off;
+    }
+    L.slot_bytes = off;
+    L.off_order = kCoHeader;
+    L.off_slots = align_up(kCoHeader + (size_t)std::max(npairs, 1) * 4, 256);
+    const int64_t resident = (int64_t)di.cus * kCoBlocksPerCu * kCoWaves;
+    const int64_t needed = ((int64_t)std::max(npairs, 1) + kCoWaves - 1) / kCoWaves * kCoWaves;
+    L.full_slots = std::min(resident, needed);
+    return L;
+}
+
+}  // namespace
+
+size_t cooptimal_workspace_bytes(int32_t npairs, int32_t max_len, int32_t k, const DeviceInfo& di) {
+    const CoLayout L = co_layout(npairs, max_len, k, di);
+    return L.off_slots + (size_t)L.full_slots * (size_t)L.slot_bytes;
+}
+
+int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
+                     const int64_t* b_off, const int32_t* b_len, int32_t max_len, const nw_scoring& sc,
+                     int32_t* scores, uint64_t* counts, uint8_t* saturated, int32_t k, uint8_t* paths,
+                     const int64_t* path_off, int32_t* path_len, int32_t* n_paths, void* ws, size_t ws_bytes,
+                     hipStream_t st, const DeviceInfo& di) {
+    const CoLayout L = co_layout(npairs, max_len, k, di);
+    if (ws_bytes < L.off_slots + (size_t)kCoWaves * (size_t)L.slot_bytes) return NW_ENOSPC;
+    int64_t slots = std::min<int64_t>(L.full_slots, (int64_t)((ws_bytes - L.off_slots) / (size_t)L.slot_bytes));
+    slots = slots / kCoWaves * kCoWaves;
+    uint8_t* base = (uint8_t*)ws;
+    const Consts K = score_consts(sc);
+    CoArgs A{};
+    A.npairs = npairs;
+    A.pool = pool;
+    A.a_off = a_off;
+    A.a_len = a_len;
+    A.b_off = b_off;
+    A.b_len = b_len;
+    A.max_len = std::max(max_len, 1);
+    A.kdm = K.kdm;
+    A.kdx = K.kdx;
+    A.gap = sc.gap;
+    A.scores = scores;
+    A.counts = counts;
+    A.saturated = saturated;
+    A.k = k;
+    A.paths = paths;
+    A.path_off = path_off;
+    A.path_len = path_len;
+    A.n_paths = n_paths;
+    A.hist = (int32_t*)base;
+    A.cursor = A.hist + kCoBuckets;
+    A.next_job = A.cursor + kCoBuckets;
+    A.order = (int32_t*)(base + L.off_order);
+    A.slots = base + L.off_slots;
+    A.slot_bytes = L.slot_bytes;
+    A.off_tie = L.off_tie;
+    A.off_walk = L.off_walk;
+    const unsigned pg = (unsigned)((npairs + 255) / 256);
+    hipLaunchKernelGGL(k_co_zero, dim3((2 * kCoBuckets + 1 + 255) / 256), dim3(256), 0, st, A.hist,
+                       2 * kCoBuckets + 1);
+    hipLaunchKernelGGL(k_co_hist, dim3(pg), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_co_scan, dim3(1), dim3(kCoBuckets), 0, st, A);
+    hipLaunchKernelGGL(k_co_scatter, dim3(pg), dim3(256), 0, st, A);
+    {
+        ProfScope ps(k > 0 ? "nw_cooptimal_paths" : "nw_cooptimal", st);
+        const dim3 grid((unsigned)(slots / kCoWaves));
+        if (k > 0)
+            hipLaunchKernelGGL(k_count<true>, grid, dim3(kWave * kCoWaves), 0, st, A);
+        else
+            hipLaunchKernelGGL(k_count<false>, grid, dim3(kWave * kCoWaves), 0, st, A);
+    }
+    return hipGetLastError() == hipSuccess ? NW_OK : NW_EDEVICE;
+}
+
+}  // namespace nw

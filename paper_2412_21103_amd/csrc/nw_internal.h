@@ -94,6 +94,14 @@ int launch_center_star(int32_t nseq, const uint8_t* pool, const int64_t* off, co
                        int64_t width_cap, int64_t* width, void* ws, size_t ws_bytes, hipStream_t st,
                        const DeviceInfo& di);
 
+// Co-optimal alignment counts and enumeration (nw_coopt.hip).
+size_t cooptimal_workspace_bytes(int32_t npairs, int32_t max_len, int32_t k, const DeviceInfo& di);
+int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const int32_t* a_len,
+                     const int64_t* b_off, const int32_t* b_len, int32_t max_len, const nw_scoring& sc,
+                     int32_t* scores, uint64_t* counts, uint8_t* saturated, int32_t k, uint8_t* paths,
+                     const int64_t* path_off, int32_t* path_len, int32_t* n_paths, void* ws, size_t ws_bytes,
+                     hipStream_t st, const DeviceInfo& di);
+
 // Sweep-width cost table (per device), filled by nw_autotune.
 void set_step_costs(int device, const int32_t dirs[3], const int32_t score[3]);
 void reset_step_costs();
