@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs * SIMDs * lanes * clock: 39.32 T lane-ops/s
 FILL_OPS_PER_CELL = 5  # diagonal term, vertical add, max3, tag clear, tag shift
+# counting optimal paths: diagonal term, max, three equality tests, six 32-bit selects, two 64-bit adds
+COUNT_OPS_PER_CELL = 13
 KERNEL_SOURCES = ["paper_2412_21103_amd/csrc/nw_common.h", "paper_2412_21103_amd/csrc/nw_strip.h",
                   "paper_2412_21103_amd/csrc/nw_single.hip"]
 COUNTERS = os.path.join(ROOT, "profiles", "fill_coop_long_pair_65536.counters.json")
@@ -290,6 +292,88 @@ def bench_allpairs(args):
     return common_fields(args, cells / (ms * 1e-3) / 1e9, ms, config, roof, cpu)
 
 
+def bench_cooptimal(args):
+    """Co-optimal alignments of the 4096-pair batch: the number of optimal
+    paths of every pair per step (counts only), and beside it the first four
+    paths of every pair."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_2412_21103_amd as nwp
+    from workloads import config_batch, pack_pairs
+
+    print("bench: generating the 4096-pair batch", file=sys.stderr, flush=True)
+    pairs = config_batch()
+    pool, ao, al, bo, bl = pack_pairs(pairs)
+    npairs = len(pairs)
+    max_len = int(max(al.max(), bl.max()))
+    cells = int((al.astype(np.int64) * bl.astype(np.int64)).sum())
+    dev = torch.device("cuda", 0)
+    t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to(dev)
+    d = [t(pool, np.uint8), t(ao, np.int64), t(al, np.int32), t(bo, np.int64), t(bl, np.int32)]
+    scores = torch.empty(npairs, dtype=torch.int32, device=dev)
+    counts = torch.empty(npairs, dtype=torch.int64, device=dev)
+    sat = torch.empty(npairs, dtype=torch.uint8, device=dev)
+    ws_bytes = nwp.cooptimal_workspace_size(npairs, max_len, 0)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    L = nwp.lib()
+    sc = nwp.Scoring(*nwp.PAPER_SCORING)
+    stream = torch.cuda.current_stream()
+    vp = ctypes.c_void_p
+    ptr = lambda x: vp(x.data_ptr())
+    null = vp(0)
+
+    def step():
+        st = L.nw_cooptimal(npairs, *[ptr(x) for x in d], max_len, sc, ptr(scores), ptr(counts), ptr(sat), 0,
+                            null, null, null, null, ptr(ws), ws_bytes, vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_cooptimal")
+
+    ms, prof = timed_steps(step, args, torch.cuda.synchronize)
+    k = prof.get("nw_cooptimal")
+    roof = alu_roofline("nw_cooptimal", cells, k[1] / k[0] if k else None, COUNT_OPS_PER_CELL)
+    # the first four paths of every pair, same pairs
+    kp = 4
+    print(f"bench: counts + first {kp} paths", file=sys.stderr, flush=True)
+    wsk = torch.empty(nwp.cooptimal_workspace_size(npairs, max_len, kp), dtype=torch.uint8, device=dev)
+    out = nwp.cooptimal(*d, max_len, nwp.PAPER_SCORING, k=kp, workspace=wsk)
+    torch.cuda.synchronize()
+    nwp.profile_begin()
+    for _ in range(2):
+        out = nwp.cooptimal(*d, max_len, nwp.PAPER_SCORING, k=kp, workspace=wsk)
+    torch.cuda.synchronize()
+    kprof = nwp.profile_end().get("nw_cooptimal_paths")
+    paths_ms = round(kprof[1] / kprof[0], 4) if kprof else None
+    npaths = out[6].cpu().numpy()
+    same = bool(torch.equal(out[0], scores) and torch.equal(out[1], counts) and torch.equal(out[2], sat))
+    c_gpu = counts.cpu().numpy().view(np.uint64)
+    cpu = exact = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import coopt
+        nt = oracle.max_threads()
+        print(f"bench: CPU oracle counts on the whole batch ({nt} threads)", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        s_ref, n_ref, f_ref = coopt.count_batch(pool, ao, al, bo, bl, oracle.PAPER_SCORING)
+        c1 = time.perf_counter()
+        exact = bool(np.array_equal(scores.cpu().numpy(), s_ref) and np.array_equal(c_gpu, n_ref)
+                     and np.array_equal(sat.cpu().numpy(), f_ref))
+        cpu = {"value": round(cells / (c1 - c0) / 1e9, 4), "unit": "GCUPS", "cores": nt, "kind": "oracle",
+               "sample": f"the whole batch ({cells} cells), scores + counts mod 2^64 + flags, two rows per pair, "
+                         f"OpenMP over pairs, {round(c1 - c0, 2)} s"}
+    config = {"workload": f"cooptimal_batch_{npairs}", "pairs": npairs, "cells": cells, "max_len": max_len,
+              "scoring": list(nwp.PAPER_SCORING), "counts_only": True,
+              "pairs_with_one_optimal_path": int((c_gpu == 1).sum()),
+              "median_count": float(np.median(c_gpu.astype(np.float64))),
+              "saturated_pairs": int(sat.sum().item()),
+              "first_paths_k": kp, "first_paths_kernel_ms": paths_ms,
+              "first_paths_listed": int(npaths.sum()),
+              "first_paths_counts_equal": same, "bit_exact_vs_oracle": exact}
+    return common_fields(args, cells / (ms * 1e-3) / 1e9, ms, config, roof, cpu)
+
+
 def bench_center_star(args):
     """Centre-star multiple alignment of the 512 all-pairs sequences: the
     all-pairs score matrix, then the centre pick, the 511 alignments to the
@@ -383,7 +467,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["long_pair", "batch", "allpairs", "center_star"], default="long_pair")
+    ap.add_argument("--workload", choices=["long_pair", "batch", "allpairs", "center_star", "cooptimal"], default="long_pair")
     ap.add_argument("--length", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-band", action="store_true", help="skip the learned-band batch")
@@ -413,6 +497,9 @@ def main():
         return 0
     if args.workload == "center_star":
         print(json.dumps(bench_center_star(args)), flush=True)
+        return 0
+    if args.workload == "cooptimal":
+        print(json.dumps(bench_cooptimal(args)), flush=True)
         return 0
 
     import ctypes

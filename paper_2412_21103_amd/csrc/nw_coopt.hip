@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "nw_common.h"
 #include "nw_internal.h"
@@ -36,7 +37,10 @@ namespace {
 constexpr int kCoCols = 2;                       // columns per lane
 constexpr int kCoStrip = kWave * kCoCols;        // columns per strip
 constexpr int kCoWaves = 4;                      // waves per block
-constexpr int kCoBlocksPerCu = 4;
+#ifndef NW_COOPT_BLOCKS_PER_CU
+#define NW_COOPT_BLOCKS_PER_CU 2
+#endif
+constexpr int kCoBlocksPerCu = NW_COOPT_BLOCKS_PER_CU;
 constexpr int kCoBuckets = 512;                  // 8 cost buckets per octave
 constexpr size_t kCoHeader = 8192;               // hist[512], cursor[512] and next_job (ints)
 constexpr int kMoveD = 1, kMoveU = 2, kMoveL = 3;
@@ -116,35 +120,39 @@ __global__ void k_co_scatter(CoArgs A) {
     A.order[atomicAdd(&A.cursor[b], 1)] = p;
 }
 
+// A count: the number of optimal paths modulo 2^64 (lo, hi) and a third
+// word that is 1 once the number reaches 2^64 and 0 before (the flag).
+struct Count {
+    uint32_t lo, hi, ex;
+};
+
+__device__ __forceinline__ Count pick(bool e, const Count& c) {
+    return Count{e ? c.lo : 0u, e ? c.hi : 0u, e ? c.ex : 0u};
+}
+
+// a + b on three words with the carries chained (v_add_co / v_addc_co)
+__device__ __forceinline__ Count add3w(const Count& a, const Count& b) {
+    unsigned c1, c2, c3;
+    Count r;
+    r.lo = __builtin_addc(a.lo, b.lo, 0u, &c1);
+    r.hi = __builtin_addc(a.hi, b.hi, c1, &c2);
+    r.ex = __builtin_addc(a.ex, b.ex, c2, &c3);
+    return r;
+}
+
 // One cell: the maximum of the three candidates, and the sum of the counts
-// of those equal to it.  Returns the tie bits (1 diagonal, 2 vertical,
-// 4 horizontal).  EXACT also keeps F, the OR of the summed neighbours' flags
-// and of a wrapped sum.  Without EXACT the caller only watches whether a
-// count reaches 2^62: while none does, no sum of three counts can wrap and
-// every F is 0; otherwise it recomputes the pair with EXACT.
-template <bool EXACT>
-__device__ __forceinline__ uint32_t cell(int32_t cd, int32_t wu, int32_t wl, uint64_t nd, uint64_t nu, uint64_t nl,
-                                         uint32_t fd, uint32_t fu, uint32_t fl, int32_t& w, uint64_t& n,
-                                         uint32_t& f) {
+// of those equal to it (the flag word clamped to 1, so the low words stay
+// the count modulo 2^64).  Returns the tie bits (1 diagonal, 2 vertical,
+// 4 horizontal).
+__device__ __forceinline__ uint32_t cell(int32_t cd, int32_t wu, int32_t wl, const Count& nd, const Count& nu,
+                                         const Count& nl, int32_t& w, Count& n) {
     const int32_t h = imax3(cd, wu, wl);
     const bool eD = cd == h, eU = wu == h, eL = wl == h;
-    if (EXACT) {
-        uint64_t s = eD ? nd : 0;
-        uint64_t t;
-        const bool o1 = __builtin_add_overflow(s, eU ? nu : 0, &t);
-        const bool o2 = __builtin_add_overflow(t, eL ? nl : 0, &s);
-        f = max(max(eD ? fd : 0u, eU ? fu : 0u), max(eL ? fl : 0u, (uint32_t)(o1 | o2)));
-        n = s;
-    } else {
-        n = (eD ? nd : 0) + (eU ? nu : 0) + (eL ? nl : 0);
-    }
+    n = add3w(add3w(pick(eD, nd), pick(eU, nu)), pick(eL, nl));
+    asm("v_min_u32 %0, %1, 1" : "=v"(n.ex) : "v"(n.ex));
     w = h;
     return (eD ? 1u : 0u) | (eU ? 2u : 0u) | (eL ? 4u : 0u);
 }
-
-__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
-__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
-__device__ __forceinline__ uint64_t mk64(uint32_t l, uint32_t h) { return ((uint64_t)h << 32) | l; }
 
 // A boundary cell handed from one strip to the next: W, N (low, high), F.
 struct BCell {
@@ -170,12 +178,11 @@ __device__ __forceinline__ uint32_t tie_bits(const uint32_t* tie, int64_t groups
     return (word >> (8 * (t & 3) + 4 * kk)) & 7u;
 }
 
-// The fill of one pair (m, n >= 1).  Returns, without EXACT, whether a
-// count reached 2^62 (then the caller recomputes with EXACT); the lane that
-// holds column n leaves its row-m values in w_end, n_end, f_end.
-template <bool ENUM, bool EXACT>
-__device__ bool fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int32_t m, int32_t n,
-                          int32_t& w_end, uint64_t& n_end, uint32_t& f_end) {
+// The fill of one pair (m, n >= 1).  The lane that holds column n leaves
+// its row-m values in w_end and n_end.
+template <bool ENUM>
+__device__ void fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int32_t m, int32_t n,
+                          int32_t& w_end, Count& n_end) {
     const int lane = lane_id();
     const uint8_t* a = A.pool + A.a_off[p];
     const uint8_t* b = A.pool + A.b_off[p];
@@ -185,7 +192,6 @@ __device__ bool fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int
     const int32_t steps = m + kWave - 1;
     const int64_t groups = ((int64_t)steps + 3) / 4;
     const int nstrips = (n + kCoStrip - 1) / kCoStrip;
-    uint32_t hiacc = 0;  // OR of the high words of every count
     for (int s = 0; s < nstrips; ++s) {
         const int j0 = s * kCoStrip;
         const BCell* bin = bnd + (s & 1) * bstride;
@@ -196,13 +202,11 @@ __device__ bool fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int
         // lanes past column n stay at row 0; rows run 1..m for the others
         const uint32_t rows = c0 <= n ? (uint32_t)m : 0u;
         const bool hand = lane == kWave - 1 && s + 1 < nstrips;
-        // row 0: W = 0, N = 1, F = 0 everywhere (one path along the first row)
+        // row 0: W = 0 and one path everywhere
         int32_t w0 = 0, w1 = 0;
-        uint64_t n0 = 1, n1 = 1;
-        uint32_t f0 = 0, f1 = 0;
+        Count n0{1u, 0u, 0u}, n1{1u, 0u, 0u};
         int32_t dw = 0;  // diagonal input of column 0: the last step's left input
-        uint64_t dn = 1;
-        uint32_t df = 0;
+        Count dn{1u, 0u, 0u};
         uint32_t tw = 0;
         fence_agent();  // the previous strip's column (written by lane 63) is visible
         for (int32_t T = 0; T < steps; T += kWave) {
@@ -220,43 +224,43 @@ __device__ bool fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
             const int32_t cnt = min(kWave, steps - T);
-            // one step: lane l at row T+u+1-l
-            auto step = [&](int32_t u) {
+            // this step's row word and boundary cell, read one step ahead
+            int32_t rw_next = (int32_t)S.rw[kWave - lane];
+            BCell in_next = S.col[0];
+            // one step: lane l at row T+u+1-l.  CHECK keeps lanes outside
+            // rows 1..m (and past column n) where they are; the blocks whose
+            // steps all lie in 63..m-1 have every lane inside and skip it.
+            auto step = [&](auto check, int32_t u) {
+                constexpr bool CHECK = decltype(check)::value;
                 const int32_t t = T + u;
                 const uint32_t rm1 = (uint32_t)(t - lane);  // row - 1
-                const int32_t rw = (int32_t)S.rw[kWave + u - lane];
-                const BCell in = S.col[u];
+                const int32_t rw = rw_next;
+                const BCell in = in_next;
+                const int32_t un = min(u + 1, kWave - 1);
+                rw_next = (int32_t)S.rw[kWave + un - lane];
+                in_next = S.col[un];
                 const int32_t lw = dpp_from_left(in.w, w1);
-                const uint32_t lnl = (uint32_t)dpp_from_left((int32_t)in.nl, (int32_t)lo32(n1));
-                const uint32_t lnh = (uint32_t)dpp_from_left((int32_t)in.nh, (int32_t)hi32(n1));
-                const uint32_t lf = EXACT ? (uint32_t)dpp_from_left((int32_t)in.f, (int32_t)f1) : 0u;
-                const uint64_t ln = mk64(lnl, lnh);
+                const Count ln{(uint32_t)dpp_from_left((int32_t)in.nl, (int32_t)n1.lo),
+                               (uint32_t)dpp_from_left((int32_t)in.nh, (int32_t)n1.hi),
+                               (uint32_t)dpp_from_left((int32_t)in.f, (int32_t)n1.ex)};
                 uint32_t bits = 0;
-                if (rm1 < rows) {
+                if (!CHECK || rm1 < rows) {
                     int32_t nw0, nw1;
-                    uint64_t nn0, nn1;
-                    uint32_t nf0 = 0, nf1 = 0;
+                    Count nn0, nn1;
                     const int32_t cd0 = __builtin_amdgcn_sdot4(rw, (int32_t)oh0, dw, false);
-                    const uint32_t b0 = cell<EXACT>(cd0, w0, lw, dn, n0, ln, df, f0, lf, nw0, nn0, nf0);
+                    const uint32_t b0 = cell(cd0, w0, lw, dn, n0, ln, nw0, nn0);
                     const int32_t cd1 = __builtin_amdgcn_sdot4(rw, (int32_t)oh1, w0, false);
-                    const uint32_t b1 = cell<EXACT>(cd1, w1, nw0, n0, n1, nn0, f0, f1, nf0, nw1, nn1, nf1);
+                    const uint32_t b1 = cell(cd1, w1, nw0, n0, n1, nn0, nw1, nn1);
                     w0 = nw0;
                     n0 = nn0;
                     w1 = nw1;
                     n1 = nn1;
-                    if (EXACT) {
-                        f0 = nf0;
-                        f1 = nf1;
-                    } else {
-                        hiacc |= hi32(nn0) | hi32(nn1);
-                    }
                     bits = b0 | (b1 << 4);
                     // lane 63 hands its second column to the next strip
-                    if (hand) bout[rm1 + 1] = BCell{w1, lo32(n1), hi32(n1), f1};
+                    if (hand) bout[rm1 + 1] = BCell{w1, n1.lo, n1.hi, n1.ex};
                 }
                 dw = lw;
                 dn = ln;
-                df = lf;
                 if (ENUM) {
                     tw = (tw >> 8) | (bits << 24);
                     if ((t & 3) == 3 || t == steps - 1) {
@@ -266,27 +270,34 @@ __device__ bool fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int
                 }
             };
             int32_t u = 0;
-            for (; u + 1 < cnt; u += 2) {
-                step(u);
-                step(u + 1);
+            if (T >= kWave - 1 && T + cnt <= m && rows == (uint32_t)m) {
+                const std::false_type all_in{};
+                for (; u + 1 < cnt; u += 2) {
+                    step(all_in, u);
+                    step(all_in, u + 1);
+                }
+                if (u < cnt) step(all_in, u);
+            } else {
+                const std::true_type edge{};
+                for (; u + 1 < cnt; u += 2) {
+                    step(edge, u);
+                    step(edge, u + 1);
+                }
+                if (u < cnt) step(edge, u);
             }
-            if (u < cnt) step(u);
         }
         if (s + 1 == nstrips) {
             // lanes stop at row m, so the lane holding column n has H(m,n)
             if (c0 == n) {
                 w_end = w0;
                 n_end = n0;
-                f_end = f0;
             } else if (c1 == n) {
                 w_end = w1;
                 n_end = n1;
-                f_end = f1;
             }
         }
         fence_agent();
     }
-    return (hiacc >> 30) != 0;
 }
 
 // Scalar walk state: moves, remaining options and the cell before each move.
@@ -354,21 +365,18 @@ __global__ __launch_bounds__(kWave * kCoWaves, kCoBlocksPerCu) void k_count(CoAr
         int32_t got = 0;
         if (ok) {
             int32_t w_end = 0;
-            uint64_t n_end = 1;
-            uint32_t f_end = 0;
+            Count n_end{1u, 0u, 0u};
             if (m > 0 && n > 0) {
-                const bool wrapped = fill_pair<ENUM, false>(A, slot, lds[wv], p, m, n, w_end, n_end, f_end);
-                if (__ballot(wrapped)) fill_pair<false, true>(A, slot, lds[wv], p, m, n, w_end, n_end, f_end);
+                fill_pair<ENUM>(A, slot, lds[wv], p, m, n, w_end, n_end);
                 // the lane that holds column n at row m has the result
                 const int src = ((n - 1) % kCoStrip) / kCoCols;
                 w_end = __shfl(w_end, src);
-                n_end = mk64((uint32_t)__shfl((int32_t)lo32(n_end), src),
-                             (uint32_t)__shfl((int32_t)hi32(n_end), src));
-                f_end = (uint32_t)__shfl((int32_t)f_end, src);
+                n_end = Count{(uint32_t)__shfl((int32_t)n_end.lo, src), (uint32_t)__shfl((int32_t)n_end.hi, src),
+                              (uint32_t)__shfl((int32_t)n_end.ex, src)};
             }
             score = w_end + A.gap * (m + n);
-            count = n_end;
-            flag = f_end != 0 ? 1u : 0u;
+            count = ((uint64_t)n_end.hi << 32) | n_end.lo;
+            flag = n_end.ex;
             if (ENUM && A.k > 0) {
                 const int64_t groups = ((int64_t)m + kWave - 1 + 3) / 4;
                 const uint32_t* tie = (const uint32_t*)(slot + A.off_tie);
