@@ -9,13 +9,17 @@
 // holds columns j0+2l+1 and j0+2l+2 of a 128-column strip and sweeps the rows
 // on a skewed front (lane l is at row t+1-l at step t).  Per cell it keeps
 //     W = H - gap*(i+j)   (Eq. 1 becomes W = max(Wd + s - 2gap, Wu, Wl)),
-//     N mod 2^64 and F = [N >= 2^64],
-// and N is the sum of N over the neighbours whose candidate equals the
-// maximum, F the OR of theirs and of a wrapped sum.  The left neighbour's
-// values come by DPP from lane l-1; lane 0 reads the previous strip's last
-// column, which lane 63 wrote to a per-wave boundary buffer one row per step.
-// With k > 0 the three tie bits of every cell are packed 8 per step into a
-// 32-bit word per lane every 4 steps.
+// and the count as three 32-bit words: the number of optimal paths modulo
+// 2^64 and a flag word, 1 once the number reaches 2^64.  A cell's count is
+// the sum of the counts of the neighbours whose candidate equals the maximum,
+// added with carries chained into the flag word, which is then clamped to 1
+// (so the low words stay exact modulo 2^64).  The left neighbour's values
+// come by DPP from lane l-1; lane 0 takes the previous strip's last column,
+// which lane 63 wrote to a per-wave buffer one row per step.  Every 64 steps
+// the wave stages in LDS the next 64 rows of that column and the row words
+// (substitution bytes) of the 128 rows around its front, and each step reads
+// them one step ahead.  With k > 0 the three tie bits of every cell are
+// packed 8 per step into a 32-bit word per lane every 4 steps.
 //
 // Enumeration.  The same wave then walks: path 0 takes the first optimal move
 // at every cell from (m,n); each later path goes back to the deepest cell of
