@@ -110,3 +110,98 @@ def band_cells(m: int, n: int, w: int) -> int:
 
 
 __all__ = ["applicable", "u_out", "certifies", "w_cert", "in_band", "w_path", "band_cells"]
+
+
+# ---------------------------------------------------------------------------
+# A tighter certificate from the band's own scores.
+#
+# A path that leaves band(w) does so for the first time by a vertical move
+# from the band's lowest diagonal (j - i = lo - w) or a horizontal move from
+# its highest (j - i = hi + w): a diagonal move keeps j - i.  Up to the cell P
+# it leaves from, the path stays in the band, so that part scores at most
+# H_band(P), the best score of an in-band path from (0,0) to P.  The move
+# adds gap, and the rest, from the first outside cell X = (i, j) to (m, n),
+# has at most min(m-i, n-j) diagonal moves and at least |(m-i) - (n-j)| gaps:
+#
+#     suf(X) = gap * ((m-i) + (n-j)) + min(m-i, n-j) * max(c_d - 2 gap, 0)
+#
+# bounds it for every scoring.  So every leaving path scores at most
+#
+#     U_tight(w) = max over such moves P -> X of  H_band(P) + gap + suf(X),
+#
+# and a region score S > U_tight(w) certifies the band as before.  Each term
+# is also bounded by U_out(w) (the closed form counts the same gaps), so the
+# tight bound never certifies less.
+# ---------------------------------------------------------------------------
+
+NEG = None  # outside the band
+
+
+def band_fill(a, b, w: int, scoring=PAPER_SCORING):
+    """H_band over band(w) (None outside): the best score of a path from
+    (0,0) that stays in band(w), by plain loops."""
+    match, mismatch, gap = scoring
+    m, n = len(a), len(b)
+    H = [[NEG] * (n + 1) for _ in range(m + 1)]
+    for i in range(m + 1):
+        for j in range(n + 1):
+            if not in_band(i, j, m, n, w):
+                continue
+            if i == 0 and j == 0:
+                H[i][j] = 0
+                continue
+            best = None
+            if i > 0 and j > 0 and H[i - 1][j - 1] is not None:
+                best = H[i - 1][j - 1] + (match if a[i - 1] == b[j - 1] else mismatch)
+            if i > 0 and H[i - 1][j] is not None:
+                c = H[i - 1][j] + gap
+                best = c if best is None else max(best, c)
+            if j > 0 and H[i][j - 1] is not None:
+                c = H[i][j - 1] + gap
+                best = c if best is None else max(best, c)
+            H[i][j] = best
+    return H
+
+
+def suffix_bound(i: int, j: int, m: int, n: int, scoring=PAPER_SCORING) -> int:
+    match, mismatch, gap = scoring
+    cd = max(match, mismatch)
+    r, c = m - i, n - j
+    return gap * (r + c) + min(r, c) * max(cd - 2 * gap, 0)
+
+
+def u_tight(a, b, w: int, scoring=PAPER_SCORING):
+    """``(S_band, U_tight)``: the best in-band score of (m,n) and the bound on
+    every path that leaves band(w) (None if no path can leave it)."""
+    gap = scoring[2]
+    m, n = len(a), len(b)
+    H = band_fill(a, b, w, scoring)
+    d = n - m
+    lo, hi = min(0, d) - w, max(0, d) + w
+    best = None
+    for i in range(m + 1):
+        for j in range(n + 1):
+            if H[i][j] is None:
+                continue
+            if j - i == lo and i + 1 <= m:      # vertical move out of the band
+                t = H[i][j] + gap + suffix_bound(i + 1, j, m, n, scoring)
+                best = t if best is None else max(best, t)
+            if j - i == hi and j + 1 <= n:      # horizontal move out of the band
+                t = H[i][j] + gap + suffix_bound(i, j + 1, m, n, scoring)
+                best = t if best is None else max(best, t)
+    return H[m][n], best
+
+
+def certifies_tight(a, b, w: int, scoring=PAPER_SCORING) -> bool:
+    s, u = u_tight(a, b, w, scoring)
+    return True if u is None else s > u
+
+
+def w_cert_tight(a, b, scoring=PAPER_SCORING) -> int:
+    """Smallest w >= 0 that the tight bound certifies (min(m, n) at most:
+    there no path can leave)."""
+    m, n = len(a), len(b)
+    for w in range(0, min(m, n) + 1):
+        if certifies_tight(a, b, w, scoring):
+            return w
+    return min(m, n)
