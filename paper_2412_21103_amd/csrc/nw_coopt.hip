@@ -172,6 +172,21 @@ struct WaveLds {
     BCell col[kWave];
 };
 
+// Everything a wave hands to itself through global memory (the strip
+// boundary, the tie words, the walk's state) is read back by the same wave,
+// on the same CU: a workgroup-scope fence (its stores complete) and loads
+// that bypass L1 suffice; no L2 writeback is needed.
+__device__ __forceinline__ void fence_wave_mem() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ BCell load_bcell(const BCell* p) {
+    const int32_t* q = (const int32_t*)p;
+    return BCell{load_coherent(q), (uint32_t)load_coherent(q + 1), (uint32_t)load_coherent(q + 2),
+                 (uint32_t)load_coherent(q + 3)};
+}
+
 // Tie bits of cell (i,j), 1 <= i <= m, 1 <= j <= n, from the packed words of
 // the fill (strip s, group g of 4 steps, lane l).
 __device__ __forceinline__ uint32_t tie_bits(const uint32_t* tie, int64_t groups, int32_t i, int32_t j) {
@@ -212,14 +227,14 @@ __device__ void fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int
         int32_t dw = 0;  // diagonal input of column 0: the last step's left input
         Count dn{1u, 0u, 0u};
         uint32_t tw = 0;
-        fence_agent();  // the previous strip's column (written by lane 63) is visible
+        fence_wave_mem();  // the previous strip's column (written by lane 63) is visible
         for (int32_t T = 0; T < steps; T += kWave) {
             {
                 const int32_t r = T + 1 + lane;
                 const uint32_t older = T == 0 ? 0u : S.rw[kWave + lane];
                 const uint32_t word = r <= m ? row_word(a[r - 1] & 3u, A.kdm, A.kdx) : 0u;
                 BCell c{0, 1u, 0u, 0u};
-                if (s > 0 && r <= m) c = bin[r];
+                if (s > 0 && r <= m) c = load_bcell(bin + r);
                 __builtin_amdgcn_wave_barrier();
                 S.rw[lane] = older;
                 S.rw[kWave + lane] = word;
@@ -300,7 +315,7 @@ __device__ void fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int
                 n_end = n1;
             }
         }
-        fence_agent();
+        fence_wave_mem();
     }
 }
 
@@ -338,7 +353,7 @@ __device__ int32_t descend(const uint32_t* tie, int64_t groups, const Walk& W, i
 }
 
 __device__ void emit_path(const CoArgs& A, const Walk& W, int p, int r, int32_t m, int32_t n, int32_t len) {
-    fence_agent();
+    fence_wave_mem();
     uint8_t* out = A.paths + A.path_off[p] + (int64_t)r * (m + n);
     for (int32_t x = lane_id(); x < len; x += kWave)
         out[x] = (uint8_t)__hip_atomic_load(W.mv + (len - 1 - x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -388,12 +403,12 @@ __global__ __launch_bounds__(kWave * kCoWaves, kCoBlocksPerCu) void k_count(CoAr
                 Walk W{slot + A.off_walk, slot + A.off_walk + L, nullptr, nullptr};
                 W.ci = (int32_t*)(slot + A.off_walk + ((2 * (int64_t)L + 15) & ~(int64_t)15));
                 W.cj = W.ci + L;
-                fence_agent();
+                fence_wave_mem();
                 int32_t d = descend(tie, groups, W, m, n, 0);
                 emit_path(A, W, p, 0, m, n, d);
                 got = 1;
                 while (got < A.k) {
-                    fence_agent();
+                    fence_wave_mem();
                     // deepest position with an untried move, 64 positions at a time
                     int32_t q = -1;
                     for (int32_t hi = d - 1; hi >= 0 && q < 0; hi -= kWave) {
@@ -410,7 +425,7 @@ __global__ __launch_bounds__(kWave * kCoWaves, kCoBlocksPerCu) void k_count(CoAr
                         (int32_t)__hip_atomic_load(W.alt + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
                     const uint32_t bit = o & (0u - o);
                     const int mv = bit == 1u ? kMoveD : (bit == 2u ? kMoveU : kMoveL);
-                    fence_agent();  // every lane has read alt[q] before any lane rewrites it
+                    fence_wave_mem();  // every lane has read alt[q] before any lane rewrites it
                     W.mv[q] = (uint8_t)mv;
                     W.alt[q] = (uint8_t)(o & ~bit);
                     d = descend(tie, groups, W, i - (mv != kMoveL ? 1 : 0), j - (mv != kMoveU ? 1 : 0), q + 1);
