@@ -46,7 +46,9 @@ constexpr int kCoWaves = 4;                      // waves per block
 #endif
 constexpr int kCoBlocksPerCu = NW_COOPT_BLOCKS_PER_CU;
 constexpr int kCoBuckets = 512;                  // 8 cost buckets per octave
-constexpr size_t kCoHeader = 8192;               // hist[512], cursor[512] and next_job (ints)
+constexpr size_t kCoHeader = 8192;               // hist[512], cursor[512], next_job, next_team, n_team (ints)
+constexpr int kCoHeaderInts = 2 * kCoBuckets + 3;
+constexpr int kTeamRing = 8;                     // boundary columns in flight per team
 constexpr int kMoveD = 1, kMoveU = 2, kMoveL = 3;
 
 struct CoArgs {
@@ -69,7 +71,10 @@ struct CoArgs {
     int32_t* n_paths;
     int32_t* hist;
     int32_t* cursor;
-    int32_t* next_job;
+    int32_t* next_job;   // solo queue: positions n_team .. npairs-1 of order
+    int32_t* next_team;  // team queue: positions 0 .. n_team-1
+    int32_t* n_team;
+    int32_t team_bucket;  // pairs in this cost bucket or above go to teams
     int32_t* order;
     uint8_t* slots;
     int64_t slot_bytes;
@@ -115,6 +120,9 @@ __global__ __launch_bounds__(kCoBuckets) void k_co_scan(CoArgs A) {
     }
     const int b = kCoBuckets - 1 - t;
     A.cursor[b] = s[t] - A.hist[b];
+    // the team queue: every pair in a bucket at or above team_bucket, which
+    // the largest-first order puts first
+    if (b == A.team_bucket - 1) *A.n_team = s[t] - A.hist[b];
 }
 
 __global__ void k_co_scatter(CoArgs A) {
@@ -197,126 +205,172 @@ __device__ __forceinline__ uint32_t tie_bits(const uint32_t* tie, int64_t groups
     return (word >> (8 * (t & 3) + 4 * kk)) & 7u;
 }
 
-// The fill of one pair (m, n >= 1).  The lane that holds column n leaves
-// its row-m values in w_end and n_end.
+// Team hand-off between the waves of a block: a strip publishes, in LDS, how
+// many rows of its last column it has written to global memory, tagged with
+// the strip (tag = (strip+1) << 32 | rows).
+struct Hand {
+    int64_t* prog_in;   // the previous strip's counter (nullptr: solo wave)
+    int64_t* prog_out;  // this strip's counter (nullptr: nobody reads it)
+    int32_t* err;       // set when a wait gives up
+};
+
+constexpr uint32_t kSpinLimit = 1u << 22;  // polls before a wait gives up
+
+// Wait until the counter reaches `need` (every wait ends: producers never
+// wait on their consumers; the limit only guards against a fault).
+__device__ __forceinline__ void wait_rows(const int64_t* prog, int64_t need, int32_t* err) {
+    for (uint32_t it = 0;; ++it) {
+        const int64_t v = __hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int64_t vu = ((int64_t)uniform((int32_t)(v >> 32)) << 32) | (uint32_t)uniform((int32_t)v);
+        if (vu >= need) break;
+        if (it >= kSpinLimit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ void publish_rows(int64_t* prog, int s, int32_t rows) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the column's stores are done
+    __hip_atomic_store(prog, ((int64_t)(s + 1) << 32) | (uint32_t)rows, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One strip s of a pair (m, n >= 1): reads the previous strip's column from
+// `bin` (s > 0) and writes its own last column to `bout` (if not the last
+// strip).  The lane that holds column n leaves its row-m values in w_end and
+// n_end (last strip only).
+template <bool ENUM>
+__device__ void fill_strip(const CoArgs& A, WaveLds& S, const uint8_t* a, const uint8_t* b, int32_t m, int32_t n,
+                           int s, int nstrips, const BCell* bin, BCell* bout, const Hand& H, uint32_t* tie,
+                           int32_t& w_end, Count& n_end) {
+    const int lane = lane_id();
+    const int32_t steps = m + kWave - 1;
+    const int64_t groups = ((int64_t)steps + 3) / 4;
+    const int j0 = s * kCoStrip;
+    const int32_t c0 = j0 + 2 * lane + 1, c1 = c0 + 1;
+    const uint32_t oh0 = 1u << (8 * (c0 <= n ? (b[c0 - 1] & 3) : 0));
+    const uint32_t oh1 = 1u << (8 * (c1 <= n ? (b[c1 - 1] & 3) : 0));
+    // lanes past column n stay at row 0; rows run 1..m for the others
+    const uint32_t rows = c0 <= n ? (uint32_t)m : 0u;
+    const bool hand = lane == kWave - 1 && s + 1 < nstrips;
+    // row 0: W = 0 and one path everywhere
+    int32_t w0 = 0, w1 = 0;
+    Count n0{1u, 0u, 0u}, n1{1u, 0u, 0u};
+    int32_t dw = 0;  // diagonal input of column 0: the last step's left input
+    Count dn{1u, 0u, 0u};
+    uint32_t tw = 0;
+    fence_wave_mem();
+    for (int32_t T = 0; T < steps; T += kWave) {
+        {
+            const int32_t r = T + 1 + lane;
+            if (s > 0 && H.prog_in) wait_rows(H.prog_in, ((int64_t)s << 32) | (uint32_t)min(T + kWave, m), H.err);
+            const uint32_t older = T == 0 ? 0u : S.rw[kWave + lane];
+            const uint32_t word = r <= m ? row_word(a[r - 1] & 3u, A.kdm, A.kdx) : 0u;
+            BCell c{0, 1u, 0u, 0u};
+            if (s > 0 && r <= m) c = load_bcell(bin + r);
+            __builtin_amdgcn_wave_barrier();
+            S.rw[lane] = older;
+            S.rw[kWave + lane] = word;
+            S.col[lane] = c;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+        const int32_t cnt = min(kWave, steps - T);
+        // this step's row word and boundary cell, read one step ahead
+        int32_t rw_next = (int32_t)S.rw[kWave - lane];
+        BCell in_next = S.col[0];
+        // one step: lane l at row T+u+1-l.  CHECK keeps lanes outside
+        // rows 1..m (and past column n) where they are; the blocks whose
+        // steps all lie in 63..m-1 have every lane inside and skip it.
+        auto step = [&](auto check, int32_t u) {
+            constexpr bool CHECK = decltype(check)::value;
+            const int32_t t = T + u;
+            const uint32_t rm1 = (uint32_t)(t - lane);  // row - 1
+            const int32_t rw = rw_next;
+            const BCell in = in_next;
+            const int32_t un = min(u + 1, kWave - 1);
+            rw_next = (int32_t)S.rw[kWave + un - lane];
+            in_next = S.col[un];
+            const int32_t lw = dpp_from_left(in.w, w1);
+            const Count ln{(uint32_t)dpp_from_left((int32_t)in.nl, (int32_t)n1.lo),
+                           (uint32_t)dpp_from_left((int32_t)in.nh, (int32_t)n1.hi),
+                           (uint32_t)dpp_from_left((int32_t)in.f, (int32_t)n1.ex)};
+            uint32_t bits = 0;
+            if (!CHECK || rm1 < rows) {
+                int32_t nw0, nw1;
+                Count nn0, nn1;
+                const int32_t cd0 = __builtin_amdgcn_sdot4(rw, (int32_t)oh0, dw, false);
+                const uint32_t b0 = cell(cd0, w0, lw, dn, n0, ln, nw0, nn0);
+                const int32_t cd1 = __builtin_amdgcn_sdot4(rw, (int32_t)oh1, w0, false);
+                const uint32_t b1 = cell(cd1, w1, nw0, n0, n1, nn0, nw1, nn1);
+                w0 = nw0;
+                n0 = nn0;
+                w1 = nw1;
+                n1 = nn1;
+                bits = b0 | (b1 << 4);
+                // lane 63 hands its second column to the next strip
+                if (hand) bout[rm1 + 1] = BCell{w1, n1.lo, n1.hi, n1.ex};
+            }
+            dw = lw;
+            dn = ln;
+            if (ENUM) {
+                tw = (tw >> 8) | (bits << 24);
+                if ((t & 3) == 3 || t == steps - 1) {
+                    const uint32_t sh = (uint32_t)(8 * (3 - (t & 3)));
+                    tie[((int64_t)s * groups + (t >> 2)) * kWave + lane] = tw >> sh;
+                }
+            }
+        };
+        int32_t u = 0;
+        if (T >= kWave - 1 && T + cnt <= m && j0 + kCoStrip <= n) {
+            const std::false_type all_in{};
+            for (; u + 1 < cnt; u += 2) {
+                step(all_in, u);
+                step(all_in, u + 1);
+            }
+            if (u < cnt) step(all_in, u);
+        } else {
+            const std::true_type edge{};
+            for (; u + 1 < cnt; u += 2) {
+                step(edge, u);
+                step(edge, u + 1);
+            }
+            if (u < cnt) step(edge, u);
+        }
+        // lane 63 wrote row r at step r + 62
+        if (H.prog_out) publish_rows(H.prog_out, s, min(m, max(0, T + cnt - 1 - (kWave - 2))));
+    }
+    if (s + 1 == nstrips) {
+        // lanes stop at row m, so the lane holding column n has H(m,n)
+        if (c0 == n) {
+            w_end = w0;
+            n_end = n0;
+        } else if (c1 == n) {
+            w_end = w1;
+            n_end = n1;
+        }
+    }
+    fence_wave_mem();
+}
+
+// The fill of one pair (m, n >= 1) by one wave: strips in order, the
+// boundary column alternating between the two buffers of the wave's slot.
 template <bool ENUM>
 __device__ void fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int32_t m, int32_t n,
                           int32_t& w_end, Count& n_end) {
-    const int lane = lane_id();
     const uint8_t* a = A.pool + A.a_off[p];
     const uint8_t* b = A.pool + A.b_off[p];
     BCell* bnd = (BCell*)slot;  // two buffers of max_len+1 rows
     const int64_t bstride = (int64_t)A.max_len + 1;
     uint32_t* tie = (uint32_t*)(slot + A.off_tie);
-    const int32_t steps = m + kWave - 1;
-    const int64_t groups = ((int64_t)steps + 3) / 4;
     const int nstrips = (n + kCoStrip - 1) / kCoStrip;
-    for (int s = 0; s < nstrips; ++s) {
-        const int j0 = s * kCoStrip;
-        const BCell* bin = bnd + (s & 1) * bstride;
-        BCell* bout = bnd + ((s & 1) ^ 1) * bstride;
-        const int32_t c0 = j0 + 2 * lane + 1, c1 = c0 + 1;
-        const uint32_t oh0 = 1u << (8 * (c0 <= n ? (b[c0 - 1] & 3) : 0));
-        const uint32_t oh1 = 1u << (8 * (c1 <= n ? (b[c1 - 1] & 3) : 0));
-        // lanes past column n stay at row 0; rows run 1..m for the others
-        const uint32_t rows = c0 <= n ? (uint32_t)m : 0u;
-        const bool hand = lane == kWave - 1 && s + 1 < nstrips;
-        // row 0: W = 0 and one path everywhere
-        int32_t w0 = 0, w1 = 0;
-        Count n0{1u, 0u, 0u}, n1{1u, 0u, 0u};
-        int32_t dw = 0;  // diagonal input of column 0: the last step's left input
-        Count dn{1u, 0u, 0u};
-        uint32_t tw = 0;
-        fence_wave_mem();  // the previous strip's column (written by lane 63) is visible
-        for (int32_t T = 0; T < steps; T += kWave) {
-            {
-                const int32_t r = T + 1 + lane;
-                const uint32_t older = T == 0 ? 0u : S.rw[kWave + lane];
-                const uint32_t word = r <= m ? row_word(a[r - 1] & 3u, A.kdm, A.kdx) : 0u;
-                BCell c{0, 1u, 0u, 0u};
-                if (s > 0 && r <= m) c = load_bcell(bin + r);
-                __builtin_amdgcn_wave_barrier();
-                S.rw[lane] = older;
-                S.rw[kWave + lane] = word;
-                S.col[lane] = c;
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            }
-            const int32_t cnt = min(kWave, steps - T);
-            // this step's row word and boundary cell, read one step ahead
-            int32_t rw_next = (int32_t)S.rw[kWave - lane];
-            BCell in_next = S.col[0];
-            // one step: lane l at row T+u+1-l.  CHECK keeps lanes outside
-            // rows 1..m (and past column n) where they are; the blocks whose
-            // steps all lie in 63..m-1 have every lane inside and skip it.
-            auto step = [&](auto check, int32_t u) {
-                constexpr bool CHECK = decltype(check)::value;
-                const int32_t t = T + u;
-                const uint32_t rm1 = (uint32_t)(t - lane);  // row - 1
-                const int32_t rw = rw_next;
-                const BCell in = in_next;
-                const int32_t un = min(u + 1, kWave - 1);
-                rw_next = (int32_t)S.rw[kWave + un - lane];
-                in_next = S.col[un];
-                const int32_t lw = dpp_from_left(in.w, w1);
-                const Count ln{(uint32_t)dpp_from_left((int32_t)in.nl, (int32_t)n1.lo),
-                               (uint32_t)dpp_from_left((int32_t)in.nh, (int32_t)n1.hi),
-                               (uint32_t)dpp_from_left((int32_t)in.f, (int32_t)n1.ex)};
-                uint32_t bits = 0;
-                if (!CHECK || rm1 < rows) {
-                    int32_t nw0, nw1;
-                    Count nn0, nn1;
-                    const int32_t cd0 = __builtin_amdgcn_sdot4(rw, (int32_t)oh0, dw, false);
-                    const uint32_t b0 = cell(cd0, w0, lw, dn, n0, ln, nw0, nn0);
-                    const int32_t cd1 = __builtin_amdgcn_sdot4(rw, (int32_t)oh1, w0, false);
-                    const uint32_t b1 = cell(cd1, w1, nw0, n0, n1, nn0, nw1, nn1);
-                    w0 = nw0;
-                    n0 = nn0;
-                    w1 = nw1;
-                    n1 = nn1;
-                    bits = b0 | (b1 << 4);
-                    // lane 63 hands its second column to the next strip
-                    if (hand) bout[rm1 + 1] = BCell{w1, n1.lo, n1.hi, n1.ex};
-                }
-                dw = lw;
-                dn = ln;
-                if (ENUM) {
-                    tw = (tw >> 8) | (bits << 24);
-                    if ((t & 3) == 3 || t == steps - 1) {
-                        const uint32_t sh = (uint32_t)(8 * (3 - (t & 3)));
-                        tie[((int64_t)s * groups + (t >> 2)) * kWave + lane] = tw >> sh;
-                    }
-                }
-            };
-            int32_t u = 0;
-            if (T >= kWave - 1 && T + cnt <= m && rows == (uint32_t)m) {
-                const std::false_type all_in{};
-                for (; u + 1 < cnt; u += 2) {
-                    step(all_in, u);
-                    step(all_in, u + 1);
-                }
-                if (u < cnt) step(all_in, u);
-            } else {
-                const std::true_type edge{};
-                for (; u + 1 < cnt; u += 2) {
-                    step(edge, u);
-                    step(edge, u + 1);
-                }
-                if (u < cnt) step(edge, u);
-            }
-        }
-        if (s + 1 == nstrips) {
-            // lanes stop at row m, so the lane holding column n has H(m,n)
-            if (c0 == n) {
-                w_end = w0;
-                n_end = n0;
-            } else if (c1 == n) {
-                w_end = w1;
-                n_end = n1;
-            }
-        }
-        fence_wave_mem();
-    }
+    const Hand solo{nullptr, nullptr, nullptr};
+    for (int s = 0; s < nstrips; ++s)
+        fill_strip<ENUM>(A, S, a, b, m, n, s, nstrips, bnd + (s & 1) * bstride, bnd + ((s & 1) ^ 1) * bstride, solo,
+                         tie, w_end, n_end);
 }
 
 // Scalar walk state: moves, remaining options and the cell before each move.
@@ -372,8 +426,59 @@ __global__ __launch_bounds__(kWave * kCoWaves, kCoBlocksPerCu) void k_count(CoAr
     const int wv = threadIdx.x / kWave;
     const int64_t wave = (int64_t)blockIdx.x * kCoWaves + wv;
     uint8_t* slot = A.slots + wave * A.slot_bytes;
+    if (!ENUM) {
+        // Teams: the four waves of the block share the largest pairs, wave w
+        // taking strips w, w+4, ...  Strip s writes its last column to ring
+        // buffer s % 8 (the two buffers of each of the block's four slots) and
+        // publishes its progress in prog[s % 8]; strip s+8 reuses the buffer
+        // only after strip s+4 has finished, which needs strip s+1 finished.
+        __shared__ int64_t prog[kTeamRing];
+        __shared__ int32_t team_job, team_err;
+        const int64_t bstride = (int64_t)A.max_len + 1;
+        uint8_t* block_slots = A.slots + (int64_t)blockIdx.x * kCoWaves * A.slot_bytes;
+        auto ring = [&](int c) { return (BCell*)(block_slots + (int64_t)(c >> 1) * A.slot_bytes) + (c & 1) * bstride; };
+        const int n_team = uniform(__hip_atomic_load(A.n_team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        for (;;) {
+            __syncthreads();
+            if (wv == 0) {
+                const int j = uniform(atomicAdd(A.next_team, lane == 0 ? 1 : 0));
+                team_job = j;
+                prog[lane & (kTeamRing - 1)] = 0;
+                team_err = 0;
+            }
+            __syncthreads();
+            const int job = uniform(team_job);
+            if (job >= n_team) break;
+            const int p = uniform(A.order[job]);
+            const int32_t m = uniform(A.a_len[p]), n = uniform(A.b_len[p]);
+            const int nstrips = (n + kCoStrip - 1) / kCoStrip;
+            const uint8_t* a = A.pool + A.a_off[p];
+            const uint8_t* b = A.pool + A.b_off[p];
+            int32_t w_end = 0;
+            Count n_end{1u, 0u, 0u};
+            for (int s = wv; s < nstrips; s += kCoWaves) {
+                const Hand H{s > 0 ? &prog[(s - 1) % kTeamRing] : nullptr,
+                             s + 1 < nstrips ? &prog[s % kTeamRing] : nullptr, &team_err};
+                fill_strip<false>(A, lds[wv], a, b, m, n, s, nstrips, s > 0 ? ring((s - 1) % kTeamRing) : nullptr,
+                                  ring(s % kTeamRing), H, nullptr, w_end, n_end);
+            }
+            __syncthreads();
+            if (wv == (nstrips - 1) % kCoWaves) {
+                const int src = ((n - 1) % kCoStrip) / kCoCols;
+                w_end = __shfl(w_end, src);
+                n_end = Count{(uint32_t)__shfl((int32_t)n_end.lo, src), (uint32_t)__shfl((int32_t)n_end.hi, src),
+                              (uint32_t)__shfl((int32_t)n_end.ex, src)};
+                const bool bad = uniform(team_err) != 0;
+                // every lane of the wave, the same values
+                A.scores[p] = bad ? INT32_MIN : w_end + A.gap * (m + n);
+                A.counts[p] = bad ? 0 : (((uint64_t)n_end.hi << 32) | n_end.lo);
+                A.saturated[p] = bad ? 0 : (uint8_t)n_end.ex;
+            }
+        }
+    }
+    const int first = ENUM ? 0 : uniform(__hip_atomic_load(A.n_team, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     for (;;) {
-        const int job = uniform(atomicAdd(A.next_job, lane == 0 ? 1 : 0));
+        const int job = first + uniform(atomicAdd(A.next_job, lane == 0 ? 1 : 0));
         if (job >= A.npairs) break;
         const int p = uniform(A.order[job]);
         const int32_t m = uniform(A.a_len[p]), n = uniform(A.b_len[p]);
@@ -512,14 +617,17 @@ int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, 
     A.hist = (int32_t*)base;
     A.cursor = A.hist + kCoBuckets;
     A.next_job = A.cursor + kCoBuckets;
+    A.next_team = A.next_job + 1;
+    A.n_team = A.next_job + 2;
+    // pairs of 2^20 cells or more are filled by teams (counts only)
+    A.team_bucket = k > 0 ? kCoBuckets : 8 * 20;
     A.order = (int32_t*)(base + L.off_order);
     A.slots = base + L.off_slots;
     A.slot_bytes = L.slot_bytes;
     A.off_tie = L.off_tie;
     A.off_walk = L.off_walk;
     const unsigned pg = (unsigned)((npairs + 255) / 256);
-    hipLaunchKernelGGL(k_co_zero, dim3((2 * kCoBuckets + 1 + 255) / 256), dim3(256), 0, st, A.hist,
-                       2 * kCoBuckets + 1);
+    hipLaunchKernelGGL(k_co_zero, dim3((kCoHeaderInts + 255) / 256), dim3(256), 0, st, A.hist, kCoHeaderInts);
     hipLaunchKernelGGL(k_co_hist, dim3(pg), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_co_scan, dim3(1), dim3(kCoBuckets), 0, st, A);
     hipLaunchKernelGGL(k_co_scatter, dim3(pg), dim3(256), 0, st, A);
