@@ -42,9 +42,12 @@ constexpr int kCoCols = 2;                       // columns per lane
 constexpr int kCoStrip = kWave * kCoCols;        // columns per strip
 constexpr int kCoWaves = 4;                      // waves per block
 #ifndef NW_COOPT_BLOCKS_PER_CU
-#define NW_COOPT_BLOCKS_PER_CU 2
+#define NW_COOPT_BLOCKS_PER_CU 4
 #endif
 constexpr int kCoBlocksPerCu = NW_COOPT_BLOCKS_PER_CU;
+#ifndef NW_COOPT_TEAM_BUCKET
+#define NW_COOPT_TEAM_BUCKET (8 * 16)  // cost bucket of 2^16 cells
+#endif
 constexpr int kCoBuckets = 512;                  // 8 cost buckets per octave
 constexpr size_t kCoHeader = 8192;               // hist[512], cursor[512], next_job, next_team, n_team (ints)
 constexpr int kCoHeaderInts = 2 * kCoBuckets + 3;
@@ -619,8 +622,8 @@ int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, 
     A.next_job = A.cursor + kCoBuckets;
     A.next_team = A.next_job + 1;
     A.n_team = A.next_job + 2;
-    // pairs of 2^20 cells or more are filled by teams (counts only)
-    A.team_bucket = k > 0 ? kCoBuckets : 8 * 20;
+    // pairs of 2^16 cells or more are filled by teams (counts only)
+    A.team_bucket = k > 0 ? kCoBuckets : NW_COOPT_TEAM_BUCKET;
     A.order = (int32_t*)(base + L.off_order);
     A.slots = base + L.off_slots;
     A.slot_bytes = L.slot_bytes;

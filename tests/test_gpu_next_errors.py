@@ -73,11 +73,13 @@ def test_cooptimal_argument_errors():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("k", [0, 3])
-def test_cooptimal_smaller_workspace_same_results(k):
+@pytest.mark.parametrize("k,lo,hi", [(0, 20, 400), (3, 20, 400), (0, 200, 1300)])
+def test_cooptimal_smaller_workspace_same_results(k, lo, hi):
+    """With k = 0 pairs of 2^16 cells or more are filled by the four waves of
+    a block; a smaller workspace runs fewer blocks and waves."""
     L = nwp.lib()
     npairs = 300
-    packed, d, ml = _pairs(61, npairs, 20, 400)
+    packed, d, ml = _pairs(61, npairs, lo, hi)
     full = nwp.cooptimal_workspace_size(npairs, ml, k)
     ws = torch.empty(full, dtype=torch.uint8, device="cuda")
     a = _outs(npairs, packed[2], packed[4], k)
