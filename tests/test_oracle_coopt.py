@@ -53,7 +53,12 @@ def test_delannoy_closed_form_and_overflow_flag():
     sc = (-2, -2, -1)
     rng = np.random.default_rng(5)
     assert len(all_paths(4, 5)) == delannoy(4, 5)
-    for m, n in [(0, 0), (0, 7), (3, 3), (6, 6), (20, 17), (35, 35), (41, 40), (60, 90), (200, 150)]:
+    # (30, 24), (44, 18): at the end cell the vertical neighbour's addition is
+    # the first sum to reach 2^64; (14, 73), (15, 63), (16, 55): only the
+    # horizontal neighbour has reached 2^64 and the sum does not wrap, so the
+    # flag must come from that neighbour
+    for m, n in [(0, 0), (0, 7), (3, 3), (6, 6), (20, 17), (35, 35), (41, 40), (60, 90), (200, 150),
+                 (30, 24), (44, 18), (14, 73), (15, 63), (16, 55)]:
         a = rng.integers(0, 4, m).astype(np.uint8)
         b = rng.integers(0, 4, n).astype(np.uint8)
         dmn = delannoy(m, n)
