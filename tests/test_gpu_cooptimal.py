@@ -152,3 +152,23 @@ def test_batch_workload_full_size():
     say(f"cooptimal counts at full size: {len(pairs)} pairs")
     packed, res = _run(pairs, P)
     _check_counts(packed, res, P)
+
+
+def test_team_shapes():
+    """Pairs of 2^16 cells or more are filled by the four waves of a block:
+    skinny and wide pairs (one to three strips), ragged last strips, and
+    pairs just below and above that size, mixed with single-wave pairs."""
+    rng = np.random.default_rng(46)
+    shapes = [(3000, 60), (60, 3000), (1500, 130), (700, 700), (256, 257), (255, 256), (1030, 1), (1, 1030),
+              (400, 513), (513, 400), (2100, 129), (90, 90), (300, 5)]
+    pairs = []
+    for m, n in shapes:
+        a = random_seq(rng, m)
+        b = mutate(rng, a, 0.1)[:n].copy() if n <= m else random_seq(rng, n)
+        if len(b) < n:
+            b = np.concatenate([b, random_seq(rng, n - len(b))])
+        pairs.append((a, b))
+    for sc in (P, TIED):
+        say(f"cooptimal team shapes, scoring {sc}")
+        packed, res = _run(pairs, sc)
+        _check_counts(packed, res, sc)
