@@ -233,7 +233,10 @@ int nw_center_star(int32_t nseq, const uint8_t *pool, const int64_t *off, const 
  * path_len and n_paths may be NULL.  npairs*k must fit in int32 (NW_ERANGE).
  *
  * A pair longer than max_len is skipped: scores = INT32_MIN, counts 0,
- * saturated 0, n_paths 0.  The workspace (caller-owned device memory) holds
+ * saturated 0, n_paths 0.  With k = 0, pairs of 2^16 cells or more are filled
+ * by the four waves of a block handing strip boundaries to each other; those
+ * waits are bounded, and a pair whose wait gave up (which only a device
+ * fault can cause) also reports INT32_MIN, 0, 0.  The workspace (caller-owned device memory) holds
  * the job order and one slot per resident wave: the boundary column, and
  * with k > 0 the tie bits of a whole pair (half a byte per cell) and the
  * walk's state.  Smaller workspaces run fewer waves, down to one block of
