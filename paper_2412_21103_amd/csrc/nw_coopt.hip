@@ -45,6 +45,11 @@ constexpr int kCoWaves = 4;                      // waves per block
 #define NW_COOPT_BLOCKS_PER_CU 4
 #endif
 constexpr int kCoBlocksPerCu = NW_COOPT_BLOCKS_PER_CU;
+// Listing paths keeps one wave per pair (no teams), so its largest pairs set
+// the time and fewer waves per SIMD serve them better; its slots (tie bits
+// for a whole pair) are also large.
+constexpr int kCoPathBlocksPerCu = 2;
+constexpr int co_blocks_per_cu(bool paths) { return paths ? kCoPathBlocksPerCu : kCoBlocksPerCu; }
 #ifndef NW_COOPT_TEAM_BUCKET
 #define NW_COOPT_TEAM_BUCKET (8 * 16)  // cost bucket of 2^16 cells
 #endif
@@ -423,7 +428,7 @@ __device__ void emit_path(const CoArgs& A, const Walk& W, int p, int r, int32_t 
 // would let the compiler split the loop per lane, and readfirstlane would
 // then stop reading lane 0.
 template <bool ENUM>
-__global__ __launch_bounds__(kWave * kCoWaves, kCoBlocksPerCu) void k_count(CoArgs A) {
+__global__ __launch_bounds__(kWave * kCoWaves, co_blocks_per_cu(ENUM)) void k_count(CoArgs A) {
     __shared__ WaveLds lds[kCoWaves];
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
@@ -574,7 +579,7 @@ CoLayout co_layout(int32_t npairs, int32_t max_len, int32_t k, const DeviceInfo&
     L.slot_bytes = off;
     L.off_order = kCoHeader;
     L.off_slots = align_up(kCoHeader + (size_t)std::max(npairs, 1) * 4, 256);
-    const int64_t resident = (int64_t)di.cus * kCoBlocksPerCu * kCoWaves;
+    const int64_t resident = (int64_t)di.cus * co_blocks_per_cu(k > 0) * kCoWaves;
     const int64_t needed = ((int64_t)std::max(npairs, 1) + kCoWaves - 1) / kCoWaves * kCoWaves;
     L.full_slots = std::min(resident, needed);
     return L;
