@@ -1,21 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the Needleman-Wunsch hot path on one MI355X.
 
-Workload: the single long pair -- a 65,536-base random ancestor and its
-10%-mutated descendant (70% substitutions, 15% insertions, 15% deletions,
-indel lengths geometric(0.5)), seeded; paper scoring +1/-1/-1; full int32
-DP with 2-bit directions and the tie-break traceback.  One step = one
-nw_align call (fill + traceback) on inputs already resident in HBM.
+Default workload (the metric's configuration): the learned-band batch --
+8192 pairs of lengths 1,000..20,000 at divergence 1..30% and indel fraction
+5..50%, seeded; paper scoring +1/-1/-1; scores and tie-break paths.  One step
+is one nw_align_batch_learned call (k-mer features, network, half-widths,
+certified banded fill with doubling and fallback, traceback) on inputs
+already resident in HBM.  The band model is trained in the same run on 4096
+pairs from disjoint seeds, with labels from the full-DP method.  Beside it on
+the same GPU and inputs: full DP (nw_align_batch) and the certified band with
+doubling from the best constant starting half-width (the method without the
+network), every score and path byte compared with full DP on the device, and
+the CPU oracle on a bounded sample of the pairs.
 
-Prints one JSON line: GCUPS (m*n cell updates per second), the fill
-kernel's roofline position (live HIP-event timing of the fill launches in
-the timed region), and the CPU oracle's rate on the same pair.
-
-The same line carries the learned-band batch beside plain full-DP batching
-(`learned_band`): 8192 pairs of lengths 1,000..20,000 at divergence 1..30%,
-the band model trained on 4096 pairs from disjoint seeds (labels from the
-full-DP method), then full-DP and learned-band runs of the whole batch with
-paths, compared for identical scores and paths on the device.
+Prints one JSON line: effective GCUPS of the learned band (full-equivalent
+m*n cells per second of wall time) as `value`, the banded kernel's roofline
+position (HIP-event timing of its launches in the timed region), and the
+oracle's rate.  Extra keys carry the single long pair (65,536 bases) and the
+single 1024-base pair.  Other workloads: --workload long_pair | single |
+batch | allpairs | center_star | cooptimal.
 """
 from __future__ import annotations
 
@@ -33,31 +36,98 @@ PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs * SIMDs * lanes * clock: 39
 FILL_OPS_PER_CELL = 5  # diagonal term, vertical add, max3, tag clear, tag shift
 # counting optimal paths: diagonal term, max, three equality tests, six 32-bit selects, two 64-bit adds
 COUNT_OPS_PER_CELL = 13
-KERNEL_SOURCES = ["paper_2412_21103_amd/csrc/nw_common.h", "paper_2412_21103_amd/csrc/nw_strip.h",
-                  "paper_2412_21103_amd/csrc/nw_single.hip"]
-COUNTERS = os.path.join(ROOT, "profiles", "fill_coop_long_pair_65536.counters.json")
+COOP_SOURCES = ["paper_2412_21103_amd/csrc/nw_common.h", "paper_2412_21103_amd/csrc/nw_strip.h",
+                "paper_2412_21103_amd/csrc/nw_single.hip"]
+BAND_SOURCES = ["paper_2412_21103_amd/csrc/nw_common.h", "paper_2412_21103_amd/csrc/nw_strip.h",
+                "paper_2412_21103_amd/csrc/nw_batch.hip"]
+COOP_COUNTERS = os.path.join(ROOT, "profiles", "fill_coop_long_pair_65536.counters.json")
+BAND_COUNTERS = os.path.join(ROOT, "profiles", "batch_banded_band_batch_8192.counters.json")
+BAND_VALU = os.path.join(ROOT, "profiles", "batch_banded_band_batch_8192.valu.json")
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_record():
-    """HBM bytes per fill launch from the committed rocprofv3 counter summary,
-    or None if the kernel sources changed since the counters were taken."""
-    if not os.path.exists(COUNTERS):
+def traffic_record(path, sources):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None if the kernel sources changed since the counters were taken."""
+    if not os.path.exists(path):
         return None
-    rec = json.load(open(COUNTERS))
-    if rec.get("kernel_hash") != kernel_hash():
+    rec = json.load(open(path))
+    if rec.get("kernel_hash") != kernel_hash(sources):
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
-def learned_band(npairs: int, warmup: int, dev, reps: int = 3):
-    """Full-DP batch vs learned certified band on the learned-band workload."""
+def valu_record(path, sources):
+    """Measured VALU instructions per cell and VALU busy fraction from a
+    committed rocprofv3 counter summary (None if the sources changed)."""
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_hash") != kernel_hash(sources):
+        return None
+    return {k: rec.get(k) for k in ("valu_lane_instr_per_cell", "valu_busy", "salu_instr_per_cell", "source")}
+
+
+def _cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def _events_timed(call, warmup, steps, sync, profile=True):
+    """W warm-up calls, then K calls each bracketed by HIP events on the
+    current stream; returns (wall ms per step, [event ms per step], kernel
+    profile of the timed calls)."""
+    import torch
+
+    import paper_2412_21103_amd as nwp
+    for _ in range(warmup):
+        call()
+    sync()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    if profile:
+        nwp.profile_begin()
+    sync()
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record()
+        call()
+        e1.record()
+    sync()
+    t1 = time.perf_counter()
+    prof = nwp.profile_end() if profile else {}
+    return (t1 - t0) * 1e3 / steps, [e0.elapsed_time(e1) for e0, e1 in ev], prof
+
+
+def _stats(ms):
+    import statistics
+    return {"median_ms": round(statistics.median(ms), 4), "min_ms": round(min(ms), 4),
+            "max_ms": round(max(ms), 4)}
+
+
+def bench_band_batch(args):
+    """The learned-band workload (the metric's configuration): 8192 pairs of
+    lengths 1,000..20,000, divergence 1..30%, indel fraction 5..50%, scores and
+    paths.  Three arms on the same inputs: (i) full DP, (ii) the certified band
+    with doubling from the best constant starting half-width (chosen on the
+    training pairs by wall time) -- the method without the network -- and
+    (iii) the learned band.  The headline is arm (iii); every arm is compared
+    with arm (i) on every score and path byte, and arm (iii) with the CPU
+    oracle on the cpu_baseline sample."""
+    import ctypes
+
     import numpy as np
     import torch
 
@@ -65,62 +135,185 @@ def learned_band(npairs: int, warmup: int, dev, reps: int = 3):
     from paper_2412_21103_amd import band_model
     from workloads import config_band_batch, pack_pairs
 
-    def to_dev(pairs):
-        pool, ao, al, bo, bl = pack_pairs(pairs)
-        t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to(dev)
-        return (t(pool, np.uint8), t(ao, np.int64), t(al, np.int32), t(bo, np.int64), t(bl, np.int32),
-                int(max(al.max(), bl.max())))
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(0)
+    npairs = args.band_pairs
+    ntrain = max(npairs // 2, 1)
+    t = lambda x, dt: torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to(dev)
 
-    print(f"bench: learned band, generating {npairs} + {npairs // 2} pairs", file=sys.stderr, flush=True)
-    test = to_dev(config_band_batch(npairs=npairs))
-    train = to_dev(config_band_batch(seed=5100, npairs=max(npairs // 2, 1)))
+    print(f"bench: learned band, generating {npairs} + {ntrain} pairs", file=sys.stderr, flush=True)
+    test_pairs = config_band_batch(npairs=npairs)
+    train_pairs = config_band_batch(seed=5100, npairs=ntrain)
+
+    class Batch:
+        def __init__(self, pairs):
+            pool, ao, al, bo, bl = pack_pairs(pairs)
+            self.host = (pool, ao, al, bo, bl)
+            self.n = len(pairs)
+            self.max_len = int(max(al.max(), bl.max()))
+            self.d = [t(pool, np.uint8), t(ao, np.int64), t(al, np.int32), t(bo, np.int64), t(bl, np.int32)]
+            caps = al.astype(np.int64) + bl.astype(np.int64)
+            self.poff_h = np.concatenate([[0], np.cumsum(caps)[:-1]]).astype(np.int64)
+            self.poff = t(self.poff_h, np.int64)
+            self.cells = float((al.astype(np.float64) * bl.astype(np.float64)).sum())
+            self.scores = torch.empty(self.n, dtype=torch.int32, device=dev)
+            self.paths = torch.empty(int(caps.sum()), dtype=torch.uint8, device=dev)
+            self.plen = torch.empty(self.n, dtype=torch.int32, device=dev)
+            self.w_used = torch.empty(self.n, dtype=torch.int32, device=dev)
+            self.status = torch.empty(self.n, dtype=torch.uint8, device=dev)
+            self.swept = torch.empty(self.n, dtype=torch.int64, device=dev)
+
+    test, train = Batch(test_pairs), Batch(train_pairs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x, _, _, target = band_model.features_and_labels(*train)
+    x, _, _, target = band_model.features_and_labels(*train.d, train.max_len)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     mlp, hist = band_model.train(x, target, epochs=200, batch=256, lr=3e-3, tau=0.9, seed=1)
     t2 = time.perf_counter()
     print(f"bench: labels {t1 - t0:.2f} s, training {t2 - t1:.2f} s, loss {hist[0]:.3f} -> {hist[-1]:.4f}",
           file=sys.stderr, flush=True)
-    del train, x, target
-    cells = float((test[2].to(torch.float64) * test[4].to(torch.float64)).sum())
-    ws = torch.empty(nwp.learned_workspace_size(npairs, test[5]), dtype=torch.uint8, device=dev)
+    del x, target
+
+    L = nwp.lib()
+    sc = nwp.Scoring(*nwp.PAPER_SCORING)
+    stream = torch.cuda.current_stream()
+    vp = ctypes.c_void_p
+    ptr = lambda x: vp(x.data_ptr()) if x is not None else vp(0)
+    frac = 0.5
     margin = 0.1
+    ws_bytes = max(nwp.learned_workspace_size(test.n, test.max_len), nwp.batch_workspace_size(test.n, test.max_len))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 
-    def run(fn):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            out = fn()
-        torch.cuda.synchronize()
-        return out, (time.perf_counter() - t0) / reps
+    def full(B):
+        st = L.nw_align_batch(B.n, *[ptr(v) for v in B.d], B.max_len, sc, 0, ptr(B.scores), ptr(B.paths),
+                              ptr(B.poff), ptr(B.plen), ptr(ws), ws_bytes, vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_align_batch")
 
-    print("bench: full-DP batch", file=sys.stderr, flush=True)
-    ref, t_full = run(lambda: nwp.align_batch(*test, workspace=ws))
-    s_ref, p_ref, poff, plen_ref = ref
-    print("bench: learned-band batch", file=sys.stderr, flush=True)
-    out, t_band = run(lambda: nwp.align_batch_learned(*test, mlp, margin, path_off=poff, workspace=ws))
-    s, p, _, plen, w_used, status, swept = out
+    def const(B, w0):
+        st = L.nw_align_batch_banded(B.n, *[ptr(v) for v in B.d], B.max_len, sc, 0, vp(0), int(w0),
+                                     ctypes.c_float(frac), ptr(B.scores), ptr(B.paths), ptr(B.poff), ptr(B.plen),
+                                     ptr(B.w_used), ptr(B.status), ptr(B.swept), ptr(ws), ws_bytes,
+                                     vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_align_batch_banded")
+
+    def learned(B):
+        st = L.nw_align_batch_learned(B.n, *[ptr(v) for v in B.d], B.max_len, sc, 0, ctypes.byref(mlp.state),
+                                      ctypes.c_float(margin), ctypes.c_float(frac), ptr(B.scores), ptr(B.paths),
+                                      ptr(B.poff), ptr(B.plen), ptr(B.w_used), ptr(B.status), ptr(B.swept),
+                                      ptr(ws), ws_bytes, vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_align_batch_learned")
+
+    sync = torch.cuda.synchronize
+
+    # arm (ii): the best constant starting half-width on the training pairs, by wall time
+    print("bench: choosing the constant starting half-width on the training pairs", file=sys.stderr, flush=True)
+    w0_ms = {}
+    for w0 in [0, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]:
+        wall, ms, _ = _events_timed(lambda: const(train, w0), 1, 2, sync, profile=False)
+        w0_ms[w0] = min(ms)
+    w0_best = min(w0_ms, key=w0_ms.get)
+
+    def snapshot(B):
+        return (B.scores.clone(), B.paths.clone(), B.plen.clone(), B.w_used.clone(), B.status.clone(),
+                B.swept.clone())
+
     # identical scores, lengths and every path byte (compared on the device)
-    plen64 = plen_ref.to(torch.int64)
-    starts = torch.repeat_interleave(poff, plen64)
-    base = torch.repeat_interleave(torch.cumsum(plen64, 0) - plen64, plen64)
-    idx = starts + torch.arange(int(plen64.sum()), device=dev) - base
-    exact = bool(torch.equal(s, s_ref) and torch.equal(plen, plen_ref) and torch.equal(p[idx], p_ref[idx]))
-    st = status.cpu().numpy()
-    return {"workload": f"band_batch_{npairs}", "pairs": npairs, "full_equivalent_cells": cells,
-            "full_dp_gcups": round(cells / t_full / 1e9, 1), "full_dp_ms": round(t_full * 1e3, 2),
-            "learned_effective_gcups": round(cells / t_band / 1e9, 1),
-            "learned_computed_gcups": round(float(swept.sum()) / t_band / 1e9, 1),
-            "learned_ms": round(t_band * 1e3, 2), "speedup_vs_full_dp": round(t_full / t_band, 3),
-            "cells_swept_frac": round(float(swept.sum()) / cells, 4),
-            "certified_first_pass": round(float(np.mean(st & 1)), 4),
-            "full_grid_frac": round(float(np.mean((st & 0x40) != 0)), 4), "margin": margin,
-            "train_pairs": max(npairs // 2, 1), "train_s": round(t2 - t1, 3), "label_dp_s": round(t1 - t0, 3),
-            "bit_exact_vs_full_dp": exact}
+    plen_idx = {}
+
+    def same(a, ref):
+        s, p, pl = a[0], a[1], a[2]
+        s_ref, p_ref, pl_ref = ref[0], ref[1], ref[2]
+        if not (torch.equal(s, s_ref) and torch.equal(pl, pl_ref)):
+            return False
+        if "idx" not in plen_idx:
+            pl64 = pl_ref.to(torch.int64)
+            starts = torch.repeat_interleave(test.poff, pl64)
+            base = torch.repeat_interleave(torch.cumsum(pl64, 0) - pl64, pl64)
+            plen_idx["idx"] = starts + torch.arange(int(pl64.sum()), device=dev) - base
+        idx = plen_idx["idx"]
+        return bool(torch.equal(p[idx], p_ref[idx]))
+
+    W, K = args.warmup, args.steps
+    print("bench: arm (i) full DP", file=sys.stderr, flush=True)
+    wall_f, ms_f, prof_f = _events_timed(lambda: full(test), W, K, sync)
+    ref = snapshot(test)
+    print(f"bench: arm (ii) certified band from w0 = {w0_best}", file=sys.stderr, flush=True)
+    wall_c, ms_c, prof_c = _events_timed(lambda: const(test, w0_best), W, K, sync)
+    out_c = snapshot(test)
+    print("bench: arm (iii) learned band", file=sys.stderr, flush=True)
+    wall_l, ms_l, prof_l = _events_timed(lambda: learned(test), W, K, sync)
+    out_l = snapshot(test)
+    exact_c, exact_l = same(out_c, ref), same(out_l, ref)
+
+    def arm(name, wall, ms, prof, out, kernel):
+        d = {"wall_ms_per_step": round(wall, 3), **_stats(ms),
+             "effective_gcups": round(test.cells / (wall * 1e-3) / 1e9, 1)}
+        if out is not None:
+            st = out[4].cpu().numpy()
+            swept = float(out[5].sum())
+            d.update({"computed_gcups": round(swept / (wall * 1e-3) / 1e9, 1),
+                      "cells_swept_frac": round(swept / test.cells, 4),
+                      "certified_first_pass": round(float(np.mean(st & 1)), 4),
+                      "doublings_mean": round(float(np.mean((st >> 1) & 31)), 3),
+                      "full_grid_frac": round(float(np.mean((st & 0x40) != 0)), 4)})
+        k = prof.get(kernel)
+        if k:
+            d["kernel"] = kernel
+            d["kernel_ms"] = round(k[1] / k[0], 4)
+        return d
+
+    res_full = arm("full", wall_f, ms_f, prof_f, None, "nw_batch")
+    res_const = arm("const", wall_c, ms_c, prof_c, out_c, "nw_batch_banded")
+    res_learned = arm("learned", wall_l, ms_l, prof_l, out_l, "nw_batch_banded")
+    res_const["w0"] = w0_best
+    res_const["w0_search_train_ms"] = {str(k): round(v, 2) for k, v in w0_ms.items()}
+
+    # roofline of the banded kernel in the learned arm: computed cells per launch
+    kb = prof_l.get("nw_batch_banded")
+    swept_cells = float(out_l[5].sum())
+    roof = alu_roofline("nw_batch_banded", swept_cells, kb[1] / kb[0] if kb else None, FILL_OPS_PER_CELL)
+    if roof:
+        roof["traffic"] = traffic_record(BAND_COUNTERS, BAND_SOURCES)
+        roof["frac_at_7_ops_per_cell"] = round(7 * swept_cells / (kb[1] / kb[0] * 1e-3) / 1e12 / PEAK_INT32_TOPS, 4)
+        roof["valu"] = valu_record(BAND_VALU, BAND_SOURCES)
+
+    cpu = exact_oracle = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nt = oracle.max_threads()
+        pool, ao, al, bo, bl = test.host
+        cum = np.cumsum(al.astype(np.float64) * bl.astype(np.float64))
+        target_cells = nt * 7e9  # about 12 s at the oracle's usual rate per thread
+        P = int(max(1, min(test.n, np.searchsorted(cum, target_cells) + 1)))
+        sub_cells = float(cum[P - 1])
+        print(f"bench: CPU oracle on the first {P} pairs ({nt} threads)", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        s_ref, p_ref = oracle.align_batch(pool, ao[:P], al[:P], bo[:P], bl[:P], oracle.PAPER_SCORING, nthreads=nt)
+        c1 = time.perf_counter()
+        s_gpu = out_l[0][:P].cpu().numpy()
+        pl = out_l[2][:P].cpu().numpy()
+        pg = out_l[1].cpu().numpy()
+        exact_oracle = bool((s_gpu == s_ref).all() and all(
+            np.array_equal(pg[test.poff_h[i]:test.poff_h[i] + pl[i]], p_ref[i]) for i in range(P)))
+        cpu = {"value": round(sub_cells / (c1 - c0) / 1e9, 4), "unit": "GCUPS", "cores": nt, "kind": "oracle",
+               "sample": f"the first {P} of the {test.n} pairs ({sub_cells:.4g} cells), full DP with scores and "
+                         f"paths, OpenMP over pairs, {round(c1 - c0, 2)} s; bit-exact against the learned band: "
+                         f"{exact_oracle}", **_cpu_info()}
+
+    config = {"workload": f"band_batch_{npairs}", "pairs": npairs, "full_equivalent_cells": test.cells,
+              "scoring": list(nwp.PAPER_SCORING), "traceback": True, "margin": margin, "fallback_frac": frac,
+              "learned_band": res_learned, "full_dp": res_full, "constant_band": res_const,
+              "speedup_learned_vs_full_dp": round(wall_f / wall_l, 3),
+              "speedup_learned_vs_constant_band": round(wall_c / wall_l, 3),
+              "bit_exact_learned_vs_full_dp": exact_l, "bit_exact_constant_vs_full_dp": exact_c,
+              "bit_exact_vs_oracle_sample": exact_oracle,
+              "train_pairs": ntrain, "train_s": round(t2 - t1, 3), "label_dp_s": round(t1 - t0, 3),
+              "train_loss": [round(hist[0], 4), round(hist[-1], 4)]}
+    return common_fields(args, test.cells / (wall_l * 1e-3) / 1e9, wall_l, config, roof, cpu)
 
 
 def common_fields(args, value, ms_per_step, config, roofline, cpu, metric_suffix=""):
@@ -462,15 +655,146 @@ def bench_center_star(args):
     return common_fields(args, cells / (ms * 1e-3) / 1e9, ms, config, roof, cpu)
 
 
+def bench_long_pair(args, length=65536, oracle_check=True):
+    """One long pair (ancestor of `length` bases, 10%-mutated descendant):
+    whole nw_align calls (fill + traceback), HIP events per call."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_2412_21103_amd as nwp
+    from workloads import config_long_pair
+
+    print(f"bench: generating the {length}-base pair", file=sys.stderr, flush=True)
+    pair = config_long_pair(length=length)
+    a, b = pair.a[0], pair.b[0]
+    m, n = int(a.shape[0]), int(b.shape[0])
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(0)
+    da = torch.from_numpy(a).to(dev)
+    db = torch.from_numpy(b).to(dev)
+    ws_bytes = nwp.align_workspace_size(m, n, 0)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    score = torch.empty(1, dtype=torch.int32, device=dev)
+    path = torch.empty(m + n, dtype=torch.uint8, device=dev)
+    plen = torch.empty(1, dtype=torch.int64, device=dev)
+    L = nwp.lib()
+    sc = nwp.Scoring(*nwp.PAPER_SCORING)
+    stream = torch.cuda.current_stream()
+    vp = ctypes.c_void_p
+
+    def step():
+        st = L.nw_align(vp(da.data_ptr()), m, vp(db.data_ptr()), n, sc, 0, vp(score.data_ptr()),
+                        vp(path.data_ptr()), m + n, vp(plen.data_ptr()), vp(ws.data_ptr()), ws_bytes,
+                        vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_align")
+
+    print(f"bench: {m} x {n}, warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr, flush=True)
+    wall, ms, prof = _events_timed(step, args.warmup, args.steps, torch.cuda.synchronize)
+    cells = m * n
+    gpu_score = int(score.item())
+    k = int(plen.item())
+    gpu_path = path[:k].cpu().numpy()
+    fill = prof.get("nw_fill_coop")
+    fill_ms = fill[1] / fill[0] if fill else None
+    tb = [prof[x] for x in ("nw_tb_spec", "nw_tb_merge", "nw_tb_fix", "nw_tb_emit") if x in prof]
+    walk_ms = sum(v[1] / v[0] for v in tb) if tb else None
+    roofline = alu_roofline("nw_fill_coop", cells, fill_ms, FILL_OPS_PER_CELL)
+    if roofline:
+        roofline["traffic"] = traffic_record(COOP_COUNTERS, COOP_SOURCES)
+        roofline["frac_at_7_ops_per_cell"] = round(7 * cells / (fill_ms * 1e-3) / 1e12 / PEAK_INT32_TOPS, 4)
+    cpu = exact = None
+    if oracle_check and not args.no_cpu_baseline:
+        import oracle
+        print("bench: CPU oracle on the same pair (one thread)", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        s_ref, p_ref = oracle.align(a, b, oracle.PAPER_SCORING, full_limit_bytes=0)
+        c1 = time.perf_counter()
+        exact = bool(s_ref == gpu_score and np.array_equal(p_ref, gpu_path))
+        cpu = {"value": round(cells / (c1 - c0) / 1e9, 4), "unit": "GCUPS", "cores": 1, "kind": "oracle",
+               "sample": f"the whole {m} x {n} pair, score + traceback, two score rows + "
+                         f"a direction byte per cell, {round(c1 - c0, 2)} s", **_cpu_info()}
+    # the anti-diagonal ramp: strip s starts a hop behind strip s-1, so the
+    # fill takes about rows + (strips - 1) * hop steps of one strip
+    config = {"workload": f"long_pair_{length}", "m": m, "n": n, "mutation_rate": 0.10,
+              "scoring": list(nwp.PAPER_SCORING), "traceback": True, **_stats(ms),
+              "fill_ms": round(fill_ms, 4) if fill_ms else None,
+              "traceback_ms": round(walk_ms, 4) if walk_ms else None,
+              "bit_exact_vs_oracle": exact}
+    return cells / (wall * 1e-3) / 1e9, wall, config, roofline, cpu
+
+
+def bench_single(args, length=1024):
+    """Two independent random sequences of `length` bases: latency of one
+    nw_align call (fill + traceback), HIP events per call.  The DP's critical
+    path is m + n - 1 dependent anti-diagonals; each needs at least two
+    dependent VALU instructions (the max and the tag clear) of 4 cycles at
+    2.4 GHz, which bounds the call from below."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_2412_21103_amd as nwp
+    from workloads import config_single
+
+    p = config_single(length=length)
+    a, b = p.a[0], p.b[0]
+    m, n = len(a), len(b)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(0)
+    da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    ws_bytes = nwp.align_workspace_size(m, n, 0)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    score = torch.empty(1, dtype=torch.int32, device=dev)
+    path = torch.empty(m + n, dtype=torch.uint8, device=dev)
+    plen = torch.empty(1, dtype=torch.int64, device=dev)
+    L = nwp.lib()
+    sc = nwp.Scoring(*nwp.PAPER_SCORING)
+    stream = torch.cuda.current_stream()
+    vp = ctypes.c_void_p
+
+    def step():
+        st = L.nw_align(vp(da.data_ptr()), m, vp(db.data_ptr()), n, sc, 0, vp(score.data_ptr()),
+                        vp(path.data_ptr()), m + n, vp(plen.data_ptr()), vp(ws.data_ptr()), ws_bytes,
+                        vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_align")
+
+    steps = max(args.steps, 20)
+    wall, ms, prof = _events_timed(step, max(args.warmup, 3), steps, torch.cuda.synchronize)
+    import statistics
+    med = statistics.median(ms)
+    cp_us = (m + n - 1) * 2 * 4 / 2.4e9 * 1e6
+    k = int(plen.item())
+    exact = None
+    if not args.no_cpu_baseline:
+        import oracle
+        s_ref, p_ref = oracle.align(a, b, oracle.PAPER_SCORING)
+        exact = bool(s_ref == int(score.item()) and np.array_equal(p_ref, path[:k].cpu().numpy()))
+    kernels = {name: round(v[1] / v[0] * 1e3, 2) for name, v in prof.items() if v[0]}
+    return {"workload": f"single_{length}", "m": m, "n": n, "median_us": round(med * 1e3, 2),
+            "min_us": round(min(ms) * 1e3, 2), "wall_us_per_call": round(wall * 1e3, 2),
+            "gcups": round(m * n / (med * 1e-3) / 1e9, 2),
+            "critical_path_steps": m + n - 1, "critical_path_bound_us": round(cp_us, 2),
+            "critical_path_frac": round(cp_us / (med * 1e3), 4), "kernel_us": kernels,
+            "bit_exact_vs_oracle": exact}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["long_pair", "batch", "allpairs", "center_star", "cooptimal"], default="long_pair")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["band_batch", "long_pair", "single", "batch", "allpairs", "center_star",
+                                           "cooptimal"], default="band_batch")
     ap.add_argument("--length", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-band", action="store_true", help="skip the learned-band batch")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="band_batch only: skip the long-pair and single-pair keys")
+    ap.add_argument("--no-band", action="store_true", help="alias of --no-extra for the other workloads")
     ap.add_argument("--band-pairs", type=int, default=8192)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first run a plain device copy of BYTES bytes (int32 elementwise), the reference "
@@ -501,111 +825,21 @@ def main():
     if args.workload == "cooptimal":
         print(json.dumps(bench_cooptimal(args)), flush=True)
         return 0
-
-    import ctypes
-
-    import numpy as np
-    import torch
-
-    import paper_2412_21103_amd as nwp
-    from workloads import config_long_pair
-
-    print(f"bench: generating the {args.length}-base pair", file=sys.stderr, flush=True)
-    pair = config_long_pair(length=args.length)
-    a, b = pair.a[0], pair.b[0]
-    m, n = int(a.shape[0]), int(b.shape[0])
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(0)
-    da = torch.from_numpy(a).to(dev)
-    db = torch.from_numpy(b).to(dev)
-    ws_bytes = nwp.align_workspace_size(m, n, 0)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    score = torch.empty(1, dtype=torch.int32, device=dev)
-    path = torch.empty(m + n, dtype=torch.uint8, device=dev)
-    plen = torch.empty(1, dtype=torch.int64, device=dev)
-    L = nwp.lib()
-    sc = nwp.Scoring(*nwp.PAPER_SCORING)
-    stream = torch.cuda.current_stream()
-    vp = ctypes.c_void_p
-
-    def step():
-        st = L.nw_align(vp(da.data_ptr()), m, vp(db.data_ptr()), n, sc, 0, vp(score.data_ptr()),
-                        vp(path.data_ptr()), m + n, vp(plen.data_ptr()), vp(ws.data_ptr()), ws_bytes,
-                        vp(stream.cuda_stream))
-        if st != 0:
-            raise nwp.NWError(st, "nw_align")
-
-    print(f"bench: {m} x {n}, warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
-    nwp.profile_begin()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = nwp.profile_end()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    cells = m * n
-    gcups = cells / (ms_per_step * 1e-3) / 1e9
-
-    gpu_score = int(score.item())
-    k = int(plen.item())
-    gpu_path = path[:k].cpu().numpy()
-
-    fill = prof.get("nw_fill_coop")
-    fill_ms = fill[1] / fill[0] if fill else None
-    tb = [prof[k] for k in ("nw_tb_spec", "nw_tb_fix", "nw_tb_emit") if k in prof]
-    walk_ms = sum(v[1] / v[0] for v in tb) if tb else None
-    roofline = None
-    if fill_ms:
-        achieved = FILL_OPS_PER_CELL * cells / (fill_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 3),
-                    "unit": "T int32 lane-ops/s", "frac": round(achieved / PEAK_INT32_TOPS, 4),
-                    "traffic": traffic_record(), "kernel": "nw_fill_coop",
-                    "kernel_ms": round(fill_ms, 4), "ops_per_cell": FILL_OPS_PER_CELL}
-
-    cpu = None
-    exact = None
-    if not args.no_cpu_baseline:
-        import oracle
-        print("bench: CPU oracle on the same pair (one thread)", file=sys.stderr, flush=True)
-        c0 = time.perf_counter()
-        s_ref, p_ref = oracle.align(a, b, oracle.PAPER_SCORING, full_limit_bytes=0)
-        c1 = time.perf_counter()
-        exact = bool(s_ref == gpu_score and np.array_equal(p_ref, gpu_path))
-        cpu = {"value": round(cells / (c1 - c0) / 1e9, 4), "unit": "GCUPS", "cores": 1,
-               "kind": "oracle",
-               "sample": f"the whole {m} x {n} pair, score + traceback, two score rows + "
-                         f"a direction byte per cell, {round(c1 - c0, 2)} s"}
-
-    band = None if args.no_band else learned_band(args.band_pairs, args.warmup, dev)
-
-    out = {
-        "metric": "GCUPS (cell updates/s) full-DP and certified learned-band, 1 MI355X, bit-exact",
-        "value": round(gcups, 3),
-        "unit": "GCUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "strong",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": f"long_pair_{args.length}", "m": m, "n": n, "mutation_rate": 0.10,
-                   "scoring": list(nwp.PAPER_SCORING), "traceback": True,
-                   "fill_ms": round(fill_ms, 4) if fill_ms else None,
-                   "traceback_ms": round(walk_ms, 4) if walk_ms else None,
-                   "bit_exact_vs_oracle": exact},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "learned_band": band,
-    }
+    if args.workload == "long_pair":
+        value, ms, config, roof, cpu = bench_long_pair(args, args.length)
+        print(json.dumps(common_fields(args, value, ms, config, roof, cpu)), flush=True)
+        return 0
+    if args.workload == "single":
+        d = bench_single(args)
+        med = d["median_us"] * 1e-3
+        print(json.dumps(common_fields(args, d["gcups"], med, d, None, None)), flush=True)
+        return 0
+    out = bench_band_batch(args)
+    if not (args.no_extra or args.no_band):
+        value, ms, config, roof, cpu = bench_long_pair(args)
+        out["long_pair"] = {"gcups": round(value, 3), "ms_per_step": round(ms, 4), **config, "roofline": roof,
+                            "cpu_baseline": cpu}
+        out["single_pair"] = bench_single(args)
     print(json.dumps(out), flush=True)
     return 0
 

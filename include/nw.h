@@ -62,9 +62,50 @@ enum {
     NW_EINVAL = -1,  /* null pointer, negative length or count, bad flag   */
     NW_ERANGE = -2,  /* lengths or constants exceed the overflow guard      */
     NW_ENOSPC = -3,  /* path capacity or workspace too small                */
-    NW_EDEVICE = -4, /* HIP error while queueing work                       */
+    NW_EDEVICE = -4, /* HIP error while queueing work, or a device fault     */
+                     /* reported by earlier work (see Device faults below)  */
     NW_ENOTSUP = -5  /* no supported GPU (not gfx950) on the current device */
 };
+
+/* Device faults.  Work that has already been queued cannot return a status,
+ * so the kernels report the failures only a device fault can cause -- a
+ * bounded wait between waves that gave up (its watchdog), a stored direction
+ * tag that is not a move -- in a host-visible word per device.  The next
+ * libnw call on that device (any entry point, including the workspace-size
+ * queries) returns NW_EDEVICE, queues nothing and clears the word; nw_sync
+ * does the same after synchronising.  The affected outputs also carry the
+ * failure:
+ *   nw_align:            *score = INT32_MIN and *path_len = -3 (a wait gave
+ *                        up) or -2 (a corrupt direction tag);
+ *   nw_align_batch, nw_align_batch_banded, nw_align_batch_learned, and the
+ *   alignments inside nw_center_star:
+ *                        path_len[k] = -2 (a corrupt direction tag); these
+ *                        engines have no waits between waves;
+ *   nw_cooptimal:        scores[k] = INT32_MIN, counts[k] = 0,
+ *                        saturated[k] = 0 for a pair whose team wait gave up;
+ *   nw_center_star:      *width = -1 when some alignment was unusable.
+ * Independently of faults, path_len[k] = -1 (with scores[k] = INT32_MIN)
+ * marks a pair skipped because it exceeds max_len. */
+
+/* One-time set-up of the library on the current device: the pinned host word
+ * that device faults are reported in.  Optional -- every entry point does it
+ * on first use -- but a caller that must not have the library allocate
+ * during later calls (graph capture, allocation-free loops) calls it first.
+ * Returns NW_OK, NW_ENOTSUP, or NW_EDEVICE (including a pending fault). */
+int nw_init(void);
+
+/* Synchronise `stream` (a hipStream_t; NULL = the null stream), then report
+ * a pending device fault on the current device as NW_EDEVICE (and clear it). */
+int nw_sync(void *stream);
+
+/* Testing hook for the fault path: the number of polls a bounded wait between
+ * waves makes before it gives up (default 2^22, far beyond any legitimate
+ * wait; 0 restores the default).  Applies to calls queued afterwards.  A tiny
+ * limit makes the waits of multi-wave calls (nw_align with n >= 512,
+ * nw_cooptimal team pairs) give up early: every kernel still drains and exits
+ * normally, the outputs carry the failure values above, and the fault is
+ * reported.  polls < 0 is NW_EINVAL. */
+int nw_set_wait_limit(int32_t polls);
 
 /* Flags. */
 #define NW_SCORE_ONLY 0x1u /* no traceback: paths, path_off, path_len may be NULL */
@@ -95,7 +136,12 @@ int nw_version(void);
  * nw_align: a[m], b[n] (device, codes 0..3); *score (device int32) gets
  * H(m,n); unless NW_SCORE_ONLY, path[path_cap] (device) gets the moves and
  * *path_len (device int64) their number.  path_cap >= m + n is required
- * (NW_ENOSPC otherwise).  m == 0 or n == 0 is valid.
+ * (NW_ENOSPC otherwise).  m == 0 or n == 0 is valid.  With n >= 512 the
+ * columns are split into strips swept by different waves that hand their
+ * boundaries over through bounded waits; a wait that gives up (which only a
+ * device fault can cause) yields *score = INT32_MIN and *path_len = -3 and is
+ * reported as a device fault (above).  The call may be captured into a HIP
+ * graph: each launch, replays included, tags its boundary slots afresh.
  * ------------------------------------------------------------------------ */
 int nw_align_workspace_size(int64_t m, int64_t n, uint32_t flags, size_t *bytes);
 

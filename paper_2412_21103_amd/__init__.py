@@ -20,7 +20,8 @@ __all__ = [
     "declared_functions", "MOVE_D", "MOVE_U", "MOVE_L", "SCORE_ONLY", "GRAPH", "profile_begin",
     "profile_end", "align_batch_banded", "banded_workspace_size", "Mlp", "MLP_INPUTS",
     "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_widths", "band_labels", "mlp_train_step",
-    "mlp_train_epoch", "align_batch_learned", "learned_workspace_size", "autotune",
+    "mlp_train_epoch", "align_batch_learned", "learned_workspace_size", "autotune", "init", "sync",
+    "set_wait_limit",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -103,6 +104,11 @@ def lib():
         L.nw_cooptimal_workspace_size.argtypes = [_i32, _i32, _i32, ctypes.POINTER(_sz)]
         L.nw_cooptimal.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _vp, _vp, _vp, _i32, _vp, _vp,
                                    _vp, _vp, _vp, _sz, _vp]
+        L.nw_init.restype = ctypes.c_int
+        L.nw_sync.argtypes = [_vp]
+        L.nw_sync.restype = ctypes.c_int
+        L.nw_set_wait_limit.argtypes = [_i32]
+        L.nw_set_wait_limit.restype = ctypes.c_int
         L.nw_release_caches.restype = None
         L.nw_profile_begin.restype = ctypes.c_int
         L.nw_profile_end.argtypes = [ctypes.POINTER(KernelTime), _i32, ctypes.POINTER(_i32)]
@@ -490,6 +496,23 @@ def allpairs(pool: torch.Tensor, off: torch.Tensor, lens: torch.Tensor, max_len:
                                   _ptr(out), _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "nw_allpairs_scores")
     return out
+
+
+def init():
+    """nw_init: one-time set-up of the library on the current device."""
+    _check(lib().nw_init(), "nw_init")
+
+
+def sync(stream=None):
+    """nw_sync: synchronise the stream, then raise NWError(NW_EDEVICE) if the
+    kernels reported a device fault."""
+    _check(lib().nw_sync(_stream(stream)), "nw_sync")
+
+
+def set_wait_limit(polls: int):
+    """nw_set_wait_limit: polls a bounded wait between waves makes before it
+    gives up (0 restores the default).  A testing hook for the fault path."""
+    _check(lib().nw_set_wait_limit(int(polls)), "nw_set_wait_limit")
 
 
 def profile_begin():

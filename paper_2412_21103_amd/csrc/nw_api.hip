@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -23,6 +24,45 @@ Consts score_consts(const nw_scoring& sc) {
     return Consts{sc.match - 2 * sc.gap, sc.mismatch - 2 * sc.gap, sc.gap};
 }
 
+// ---- device-fault words and the wait limit ----
+
+namespace {
+constexpr int kMaxFaultDevices = 64;
+struct FaultWords {
+    std::once_flag once;
+    uint32_t* host = nullptr;  // pinned, one word per device
+    uint32_t* dev = nullptr;   // the same memory as the kernels address it
+};
+FaultWords& fault_words() {
+    static FaultWords f;
+    return f;
+}
+std::atomic<int32_t> g_spin_limit{kDefaultSpinLimit};
+
+// One pinned host allocation per process, made on first use.
+void init_fault_words() {
+    FaultWords& F = fault_words();
+    std::call_once(F.once, [&] {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, kMaxFaultDevices * sizeof(uint32_t), hipHostMallocMapped) != hipSuccess) return;
+        std::memset(h, 0, kMaxFaultDevices * sizeof(uint32_t));
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) d = h;
+        F.host = (uint32_t*)h;
+        F.dev = (uint32_t*)d;
+    });
+}
+}  // namespace
+
+int take_fault(int device) {
+    FaultWords& F = fault_words();
+    if (!F.host || device < 0 || device >= kMaxFaultDevices) return 0;
+    volatile uint32_t* w = F.host + device;
+    if (*w == 0) return 0;
+    *w = 0;
+    return 1;
+}
+
 int device_info(DeviceInfo* out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NW_EDEVICE;
@@ -31,7 +71,13 @@ int device_info(DeviceInfo* out) {
     out->device = dev;
     out->cus = prop.multiProcessorCount;
     out->supported = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-    return out->supported ? NW_OK : NW_ENOTSUP;
+    init_fault_words();
+    FaultWords& F = fault_words();
+    out->fault = (F.dev && dev < kMaxFaultDevices) ? F.dev + dev : nullptr;
+    out->spin_limit = g_spin_limit.load();
+    if (!out->supported) return NW_ENOTSUP;
+    // a fault reported by earlier work on this device surfaces here, once
+    return take_fault(dev) ? NW_EDEVICE : NW_OK;
 }
 
 // Host checks shared by all entry points.
@@ -176,13 +222,34 @@ const char* nw_strerror(int status) {
         case NW_EINVAL: return "invalid argument (null pointer, negative length or count, bad flag)";
         case NW_ERANGE: return "lengths or scoring constants exceed the overflow guard";
         case NW_ENOSPC: return "path capacity or workspace too small";
-        case NW_EDEVICE: return "HIP error while queueing work";
+        case NW_EDEVICE: return "HIP error while queueing work, or a device fault reported by earlier work";
         case NW_ENOTSUP: return "current device is not a gfx950 GPU";
         default: return "unknown status";
     }
 }
 
-int nw_version(void) { return 100; }
+int nw_version(void) { return 200; }
+
+int nw_init(void) {
+    DeviceInfo di;
+    const int st = device_info(&di);
+    if (st == NW_ENOTSUP) return st;
+    if (!fault_words().host) return NW_EDEVICE;
+    return st;
+}
+
+int nw_sync(void* stream) {
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return NW_EDEVICE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return NW_EDEVICE;
+    return take_fault(dev) ? NW_EDEVICE : NW_OK;
+}
+
+int nw_set_wait_limit(int32_t polls) {
+    if (polls < 0) return NW_EINVAL;
+    g_spin_limit.store(polls == 0 ? kDefaultSpinLimit : polls);
+    return NW_OK;
+}
 
 void nw_release_caches(void) {
     release_graphs();

@@ -63,6 +63,7 @@ struct KArgs {
     int64_t dirs_stride;
     uint8_t* rev;
     int64_t rev_stride;
+    uint32_t* fault;  // host-visible device-fault word (may be null)
 };
 
 struct Pair {
@@ -342,7 +343,8 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                 int64_t len = walk_any(C, dirs, m, n, G, lds, rev, band_hi);
                 fence_wave_memory();
                 if (len < 0) {
-                    plen = -2;
+                    plen = -2;  // a corrupt direction tag: only a device fault can cause it
+                    if (lane == 0) report_fault(A.fault);
                 } else {
                     uint8_t* out = A.paths + A.path_off[job];
                     for (int64_t x = lane; x < len; x += kWave) out[x] = rev[len - 1 - x];
@@ -530,6 +532,7 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.dirs_stride = L.dirs_stride;
     A.rev = base + L.off_rev;
     A.rev_stride = L.rev_stride;
+    A.fault = di.fault;
 
     const unsigned pb = (unsigned)((job.njobs + 255) / 256);
     constexpr int kHeaderInts = (int)(kHeaderBytes / 4);

@@ -90,6 +90,12 @@ __device__ __forceinline__ uint32_t load_coherent_u32(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Record a device fault in the host-visible fault word (if the library has
+// one): the next call on this device returns NW_EDEVICE.
+__device__ __forceinline__ void report_fault(uint32_t* fault) {
+    if (fault) __hip_atomic_store(fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __device__ __forceinline__ void fence_agent() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

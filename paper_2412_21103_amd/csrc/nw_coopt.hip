@@ -88,6 +88,8 @@ struct CoArgs {
     int64_t slot_bytes;
     int64_t off_tie;   // within a slot
     int64_t off_walk;  // within a slot
+    int32_t spin;      // polls before a team wait gives up
+    uint32_t* fault;   // host-visible device-fault word (may be null)
 };
 
 __device__ __forceinline__ int cost_bucket(int64_t cost) {
@@ -219,19 +221,22 @@ __device__ __forceinline__ uint32_t tie_bits(const uint32_t* tie, int64_t groups
 struct Hand {
     int64_t* prog_in;   // the previous strip's counter (nullptr: solo wave)
     int64_t* prog_out;  // this strip's counter (nullptr: nobody reads it)
-    int32_t* err;       // set when a wait gives up
+    int32_t* err;       // set when a wait gives up (LDS, shared by the team)
+    int32_t spin;       // polls before a wait gives up
 };
 
-constexpr uint32_t kSpinLimit = 1u << 22;  // polls before a wait gives up
-
 // Wait until the counter reaches `need` (every wait ends: producers never
-// wait on their consumers; the limit only guards against a fault).
-__device__ __forceinline__ void wait_rows(const int64_t* prog, int64_t need, int32_t* err) {
-    for (uint32_t it = 0;; ++it) {
+// wait on their consumers; the limit only guards against a fault).  Once any
+// wait of the team has given up (err set), every wait returns at once, so a
+// failed pair drains in a few polls per strip block instead of a full limit
+// each.
+__device__ __forceinline__ void wait_rows(const int64_t* prog, int64_t need, int32_t* err, int32_t spin) {
+    for (int32_t it = 0;; ++it) {
         const int64_t v = __hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         const int64_t vu = ((int64_t)uniform((int32_t)(v >> 32)) << 32) | (uint32_t)uniform((int32_t)v);
         if (vu >= need) break;
-        if (it >= kSpinLimit) {
+        if (uniform(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != 0) break;
+        if (it >= spin) {
             __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             break;
         }
@@ -274,7 +279,7 @@ __device__ void fill_strip(const CoArgs& A, WaveLds& S, const uint8_t* a, const 
     for (int32_t T = 0; T < steps; T += kWave) {
         {
             const int32_t r = T + 1 + lane;
-            if (s > 0 && H.prog_in) wait_rows(H.prog_in, ((int64_t)s << 32) | (uint32_t)min(T + kWave, m), H.err);
+            if (s > 0 && H.prog_in) wait_rows(H.prog_in, ((int64_t)s << 32) | (uint32_t)min(T + kWave, m), H.err, H.spin);
             const uint32_t older = T == 0 ? 0u : S.rw[kWave + lane];
             const uint32_t word = r <= m ? row_word(a[r - 1] & 3u, A.kdm, A.kdx) : 0u;
             BCell c{0, 1u, 0u, 0u};
@@ -375,7 +380,7 @@ __device__ void fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int
     const int64_t bstride = (int64_t)A.max_len + 1;
     uint32_t* tie = (uint32_t*)(slot + A.off_tie);
     const int nstrips = (n + kCoStrip - 1) / kCoStrip;
-    const Hand solo{nullptr, nullptr, nullptr};
+    const Hand solo{nullptr, nullptr, nullptr, 0};
     for (int s = 0; s < nstrips; ++s)
         fill_strip<ENUM>(A, S, a, b, m, n, s, nstrips, bnd + (s & 1) * bstride, bnd + ((s & 1) ^ 1) * bstride, solo,
                          tie, w_end, n_end);
@@ -466,7 +471,7 @@ __global__ __launch_bounds__(kWave * kCoWaves, co_blocks_per_cu(ENUM)) void k_co
             Count n_end{1u, 0u, 0u};
             for (int s = wv; s < nstrips; s += kCoWaves) {
                 const Hand H{s > 0 ? &prog[(s - 1) % kTeamRing] : nullptr,
-                             s + 1 < nstrips ? &prog[s % kTeamRing] : nullptr, &team_err};
+                             s + 1 < nstrips ? &prog[s % kTeamRing] : nullptr, &team_err, A.spin};
                 fill_strip<false>(A, lds[wv], a, b, m, n, s, nstrips, s > 0 ? ring((s - 1) % kTeamRing) : nullptr,
                                   ring(s % kTeamRing), H, nullptr, w_end, n_end);
             }
@@ -477,6 +482,7 @@ __global__ __launch_bounds__(kWave * kCoWaves, co_blocks_per_cu(ENUM)) void k_co
                 n_end = Count{(uint32_t)__shfl((int32_t)n_end.lo, src), (uint32_t)__shfl((int32_t)n_end.hi, src),
                               (uint32_t)__shfl((int32_t)n_end.ex, src)};
                 const bool bad = uniform(team_err) != 0;
+                if (bad && lane == 0) report_fault(A.fault);
                 // every lane of the wave, the same values
                 A.scores[p] = bad ? INT32_MIN : w_end + A.gap * (m + n);
                 A.counts[p] = bad ? 0 : (((uint64_t)n_end.hi << 32) | n_end.lo);
@@ -634,6 +640,8 @@ int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, 
     A.slot_bytes = L.slot_bytes;
     A.off_tie = L.off_tie;
     A.off_walk = L.off_walk;
+    A.spin = di.spin_limit;
+    A.fault = di.fault;
     const unsigned pg = (unsigned)((npairs + 255) / 256);
     hipLaunchKernelGGL(k_co_zero, dim3((kCoHeaderInts + 255) / 256), dim3(256), 0, st, A.hist, kCoHeaderInts);
     hipLaunchKernelGGL(k_co_hist, dim3(pg), dim3(256), 0, st, A);

@@ -18,13 +18,29 @@ struct Consts {
 Consts dirs_consts(const nw_scoring& sc);   // V domain: 4(s - 2 gap) + 2
 Consts score_consts(const nw_scoring& sc);  // W domain: s - 2 gap
 
-// Device facts needed to size persistent grids.
+// Device facts needed to size persistent grids, and the per-call settings
+// every launch carries: the device-fault word and the polls a bounded wait
+// makes before it gives up.
 struct DeviceInfo {
     int device;
     int cus;
     bool supported;
+    uint32_t* fault;     // device view of this device's fault word (nullptr before nw_init)
+    int32_t spin_limit;  // polls before a boundary wait gives up
 };
 int device_info(DeviceInfo* out);
+
+// Default polls before a boundary wait gives up: far beyond any legitimate
+// wait (the last strip of a long pair waits for the whole pipeline to reach
+// it, milliseconds for 65,536 columns), about 0.4 s of LDS polls or a few
+// seconds of L2 polls.
+constexpr int32_t kDefaultSpinLimit = 1 << 22;
+
+// Device faults (a bounded wait that gave up, a corrupt direction tag) are
+// reported by the kernels in a word of pinned host memory per device; the
+// next entry point on that device, or nw_sync, returns NW_EDEVICE and clears
+// it.  Kernels write it with report_fault (nw_common.h).
+int take_fault(int device);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

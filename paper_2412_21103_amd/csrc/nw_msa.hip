@@ -172,6 +172,7 @@ struct MsaArgs {
     int64_t* width;      // device copy of the width
     int64_t* width_out;
     int32_t* error;      // a path inconsistent with its pair's lengths
+    uint32_t* fault;     // host-visible device-fault word (may be null)
     uint8_t* msa;
     int64_t width_cap;
     uint8_t gap;
@@ -232,6 +233,7 @@ __global__ __launch_bounds__(1024) void k_cols(MsaArgs A) {
         const bool bad = __hip_atomic_load(A.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         A.width[0] = carry;
         if (A.width_out) A.width_out[0] = bad ? -1 : carry;
+        if (bad) report_fault(A.fault);
     }
 }
 
@@ -384,6 +386,7 @@ int launch_center_star(int32_t nseq, const uint8_t* pool, const int64_t* off, co
     A.width = width;
     A.width_out = width_out;
     A.error = error;
+    A.fault = di.fault;
     A.msa = msa;
     A.width_cap = width_cap;
     A.gap = gap;

@@ -51,8 +51,10 @@ struct CoopArgs {
     int64_t bnd_stride;
     int32_t* ticket;
     int32_t* err;
-    uint32_t epoch;
+    const uint32_t* epoch;  // this call's slot tag, written by k_prep
+    int32_t spin;           // polls before a boundary wait gives up
     int32_t* score;
+    uint32_t* fault;        // host-visible device-fault word (may be null)
 };
 
 // Dynamic LDS of a block: the waves' row tables, then one boundary ring per
@@ -69,8 +71,8 @@ struct CoopLds {
 };
 
 template <int C, bool DIRS, int IN, int OUT>
-__device__ __forceinline__ int32_t coop_sweep(const CoopArgs& A, int s, int wave, uint32_t* lds, uint32_t* dyn,
-                                              int j0, int ksel) {
+__device__ __forceinline__ int32_t coop_sweep(const CoopArgs& A, uint32_t epoch, int s, int wave, uint32_t* lds,
+                                              uint32_t* dyn, int j0, int ksel) {
     lds_u64* rings = (lds_u64*)(dyn + CoopLds<C>::kTableWordsAligned);
     lds_i32* consumed = (lds_i32*)(dyn + CoopLds<C>::kCountWord);
     uint64_t* col = A.bnd + (int64_t)s * A.bnd_stride;
@@ -84,8 +86,9 @@ __device__ __forceinline__ int32_t coop_sweep(const CoopArgs& A, int s, int wave
                                    consumed + (wave + 1) % kCoopWaves,
                                    A.m,
                                    A.vinit,
-                                   A.epoch,
-                                   A.err};
+                                   epoch,
+                                   A.err,
+                                   A.spin};
     return sweep_strip<C, DIRS>(A.a, A.m, A.b, A.n, j0, A.kdm, A.kdx, A.vinit, A.vinit, io,
                                 DIRS ? A.dirs + (size_t)s * A.G * kWave * C : nullptr, lds, ksel);
 }
@@ -97,6 +100,10 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
     const int wave = threadIdx.x >> 6;
     uint32_t* lds = dyn + wave * StripShape<C>::kLdsWords;
     constexpr int kCols = kWave * C;
+    // the slot tag of this call (k_prep advances it per launch, so replays of
+    // a captured graph never accept a previous replay's slots)
+    const uint32_t epoch = (uint32_t)uniform((int32_t)__hip_atomic_load(A.epoch, __ATOMIC_RELAXED,
+                                                                          __HIP_MEMORY_SCOPE_AGENT));
     for (;;) {
         if (threadIdx.x == 0) ticket_s = atomicAdd(A.ticket, 1);
         __syncthreads();
@@ -116,17 +123,17 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
             // input: none (first strip), the block's previous wave (LDS), or the
             // previous block's last wave (HBM); output likewise
             if (s == 0) {
-                v = last ? coop_sweep<C, DIRS, kIoNone, kIoNone>(A, s, wave, lds, dyn, j0, ksel)
-                         : coop_sweep<C, DIRS, kIoNone, kIoLds>(A, s, wave, lds, dyn, j0, ksel);
+                v = last ? coop_sweep<C, DIRS, kIoNone, kIoNone>(A, epoch, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoNone, kIoLds>(A, epoch, s, wave, lds, dyn, j0, ksel);
             } else if (wave == 0) {
-                v = last ? coop_sweep<C, DIRS, kIoGlobal, kIoNone>(A, s, wave, lds, dyn, j0, ksel)
-                         : coop_sweep<C, DIRS, kIoGlobal, kIoLds>(A, s, wave, lds, dyn, j0, ksel);
+                v = last ? coop_sweep<C, DIRS, kIoGlobal, kIoNone>(A, epoch, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoGlobal, kIoLds>(A, epoch, s, wave, lds, dyn, j0, ksel);
             } else if (wave < kCoopWaves - 1) {
-                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, s, wave, lds, dyn, j0, ksel)
-                         : coop_sweep<C, DIRS, kIoLds, kIoLds>(A, s, wave, lds, dyn, j0, ksel);
+                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, epoch, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoLds, kIoLds>(A, epoch, s, wave, lds, dyn, j0, ksel);
             } else {
-                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, s, wave, lds, dyn, j0, ksel)
-                         : coop_sweep<C, DIRS, kIoLds, kIoGlobal>(A, s, wave, lds, dyn, j0, ksel);
+                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, epoch, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoLds, kIoGlobal>(A, epoch, s, wave, lds, dyn, j0, ksel);
             }
             if (last) {
                 const int lsel = (A.n - 1 - j0) / C;
@@ -137,10 +144,13 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
     }
 }
 
-// Score-only calls: report a boundary-wait failure of the fill as INT32_MIN.
-__global__ void k_check_fill(const int32_t* err, int32_t* score) {
-    if (threadIdx.x == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+// Score-only calls: report a boundary-wait failure of the fill as INT32_MIN
+// and in the device-fault word.
+__global__ void k_check_fill(const int32_t* err, int32_t* score, uint32_t* fault) {
+    if (threadIdx.x == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         score[0] = INT32_MIN;
+        report_fault(fault);
+    }
 }
 
 // ---- parallel traceback over strips ----
@@ -166,6 +176,7 @@ struct TbArgs {
     int64_t* path_len;
     int32_t* score;
     int64_t cap;         // path capacity, m + n
+    uint32_t* fault;     // host-visible device-fault word (may be null)
 };
 
 template <int C>
@@ -466,6 +477,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_tb_emit(TbArgs T) {
         if (s == 0 && lane == 0) {
             T.score[0] = INT32_MIN;
             T.path_len[0] = T.summary[2] == 3 ? -3 : -2;
+            report_fault(T.fault);
         }
         return;
     }
@@ -485,9 +497,22 @@ __global__ __launch_bounds__(kCoopThreads) void k_tb_emit(TbArgs T) {
     }
 }
 
-__global__ void k_zero_small(int32_t* p, int n) {
-    int i = threadIdx.x;
-    if (i < n) p[i] = 0;
+// Workspace header words of the cooperative engine.
+constexpr int kHdrTicket = 0, kHdrErr = 16, kHdrSummary = 32, kHdrEpochCount = 48, kHdrEpoch = 49;
+
+// Before each fill: clear the ticket, the failure flag and the traceback
+// summary, and advance the call's slot tag.  The tag is the host's value for
+// this call plus twice a counter kept in the workspace, so eager calls (a new
+// host value each) and replays of a captured graph (the same host value, the
+// counter moves on) both get a tag no earlier launch on this workspace used.
+__global__ void k_prep(int32_t* hdr, uint32_t host_epoch) {
+    const int i = threadIdx.x;
+    if (i < kHdrEpochCount) hdr[i] = 0;
+    if (i == 0) {
+        const uint32_t c = (uint32_t)hdr[kHdrEpochCount] + 1u;
+        hdr[kHdrEpochCount] = (int32_t)c;
+        hdr[kHdrEpoch] = (int32_t)((host_epoch + 2u * c) | 1u);
+    }
 }
 
 // ---- host side ----
@@ -578,16 +603,19 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
     A.dirs = dirs ? (uint32_t*)(base + L.off_dirs) : nullptr;
     A.bnd = (uint64_t*)(base + L.off_bnd);
     A.bnd_stride = L.bnd_stride;
-    A.ticket = (int32_t*)base;
-    A.err = (int32_t*)(base + 64);
-    A.epoch = next_epoch();
+    int32_t* hdr = (int32_t*)base;
+    A.ticket = hdr + kHdrTicket;
+    A.err = hdr + kHdrErr;
+    A.epoch = (const uint32_t*)(hdr + kHdrEpoch);
+    A.spin = di.spin_limit;
     A.score = score;
-    hipLaunchKernelGGL(k_zero_small, dim3(1), dim3(64), 0, st, (int32_t*)base, 64);
+    A.fault = di.fault;
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, st, hdr, next_epoch());
     const int grid = std::max(1, std::min(L.ngroups, di.cus));
     hipError_t e = dirs ? launch_coop_kernel<true>(A, grid, st) : launch_coop_kernel<false>(A, grid, st);
     if (e != hipSuccess) return NW_EDEVICE;
     if (!dirs) {
-        hipLaunchKernelGGL(k_check_fill, dim3(1), dim3(64), 0, st, A.err, score);
+        hipLaunchKernelGGL(k_check_fill, dim3(1), dim3(64), 0, st, A.err, score, di.fault);
     } else {
         TbArgs T{};
         T.dirs = A.dirs;
@@ -604,8 +632,9 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
         T.info = (int32_t*)(base + L.off_info);
         T.info_stride = L.info_stride;
         T.fix = (int32_t*)(base + L.off_fix);
-        T.summary = (int32_t*)(base + 128);
+        T.summary = hdr + kHdrSummary;
         T.err = A.err;
+        T.fault = di.fault;
         T.path = path;
         T.path_len = path_len;
         T.score = score;

@@ -111,16 +111,11 @@ struct PlainIO {
     }
     __device__ __forceinline__ void fail() const {}
     __device__ __forceinline__ bool failed() const { return false; }
+    __device__ __forceinline__ int spin_limit() const { return 1; }
     __device__ __forceinline__ int room_probe() const { return 0; }
     __device__ __forceinline__ void wait_room(int, int&) const {}
     __device__ __forceinline__ void mark_consumed(int) const {}
 };
-
-// Polling rounds before a boundary wait gives up and raises the failure flag:
-// a watchdog far beyond any legitimate wait (the last strip of a long pair
-// waits for the whole pipeline to reach it, milliseconds for 65,536 columns),
-// about 0.4 s of LDS polls or a few seconds of L2 polls.
-constexpr int kSpinLimit = 1 << 22;
 
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(3))) int32_t lds_i32;
@@ -158,6 +153,7 @@ struct CoopIO {
     int32_t vinit;
     uint32_t epoch;
     int32_t* err;
+    int32_t spin;  // polls before a wait gives up (the watchdog)
     using Slot = uint64_t;
     // a global refill is loaded one group (32 steps, about one L2 round trip)
     // ahead; a deeper prefetch would only add lag to the hop
@@ -203,6 +199,7 @@ struct CoopIO {
     __device__ __forceinline__ bool failed() const {
         return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
+    __device__ __forceinline__ int spin_limit() const { return spin; }
     // The output ring's reader progress, read one group before it is needed.
     __device__ __forceinline__ int room_probe() const {
         if constexpr (OUT == kIoLds) return *(volatile lds_i32*)cout;
@@ -215,12 +212,12 @@ struct CoopIO {
             const int need = r_hi - kRing;
             probe = uniform(probe);
             if (__builtin_expect(probe >= need, 1)) return;
-            for (int spin = 0; probe < need; ++spin) {
-                if (spin >= kSpinLimit) {
+            for (int it = 0; probe < need; ++it) {
+                if (it >= spin) {
                     fail();
                     return;
                 }
-                if ((spin & 31) == 31 && failed()) return;
+                if ((it & 31) == 31 && failed()) return;
                 __builtin_amdgcn_s_sleep(1);
                 probe = uniform(*(volatile lds_i32*)cout);
             }
@@ -234,13 +231,16 @@ struct CoopIO {
 
 // Load slot r (for the lanes with `want`) until every such lane sees a ready
 // slot.  The loop condition is wave-uniform.  The shared failure flag is a
-// device-scope load (a round trip to L2), so it is checked only every 32 polls.
+// device-scope load (a round trip to L2), so it is checked only every 32 polls:
+// after one wait has given up, every later wait of the call returns within 32
+// polls.
 template <class IO>
 __device__ __forceinline__ typename IO::Slot wait_slot(const IO& io, int r, bool want) {
     typename IO::Slot x = io.load(r, want);
-    for (int spin = 0; spin < kSpinLimit; ++spin) {
+    const int limit = io.spin_limit();
+    for (int spin = 0; spin < limit; ++spin) {
         if (__builtin_amdgcn_ballot_w64(!io.ready(x, r, want)) == 0) return x;
-        if ((spin & 31) == 31 && io.failed()) return x;  // another wait gave up: drain quickly
+        if ((spin & 31) == 31 && io.failed()) return x;  // a wait gave up: drain quickly
         __builtin_amdgcn_s_sleep(1);
         x = io.load(r, want);
     }
@@ -315,7 +315,6 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
     int probe = io.room_probe();
 
     const int NG = sweep_groups(m);
-    const int8_t* lds8 = reinterpret_cast<const int8_t*>(lds);
 
     // 16 steps starting at step 32g + 16h, tags into acc[]
     auto half = [&](const int g, const int h, uint32_t (&acc)[C]) {
