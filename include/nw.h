@@ -120,6 +120,9 @@ int nw_set_wait_limit(int32_t polls);
  * caller's graph instead.  The library owns the cached graphs (at most 256;
  * calls beyond that run without a graph) until nw_release_caches(). */
 #define NW_GRAPH 0x2u
+/* Banded and learned batch calls: widen a failed band by doubling it rather
+ * than to the width its score certifies (see nw_align_batch_banded). */
+#define NW_BAND_DOUBLING 0x4u
 
 /* Human-readable text for a status code (static storage). */
 const char *nw_strerror(int status);
@@ -141,7 +144,9 @@ int nw_version(void);
  * boundaries over through bounded waits; a wait that gives up (which only a
  * device fault can cause) yields *score = INT32_MIN and *path_len = -3 and is
  * reported as a device fault (above).  The call may be captured into a HIP
- * graph: each launch, replays included, tags its boundary slots afresh.
+ * graph: each launch, replays included, tags its boundary slots with a value
+ * no earlier launch on the device used, so slots left in reused memory by
+ * any earlier call never count as ready.
  * ------------------------------------------------------------------------ */
 int nw_align_workspace_size(int64_t m, int64_t n, uint32_t flags, size_t *bytes);
 
@@ -182,7 +187,11 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  *     S_R > U_out(w) = c_d*(min(m,n) - w - 1) + gap*(|D| + 2w + 2),
  *     c_d = max(match, mismatch)   (valid when 2*gap < c_d),
  * which forces every optimal path inside the band, so score and tie-break
- * path equal the full grid's.  Otherwise w doubles (0 becomes 1).  The full
+ * path equal the full grid's.  Otherwise the band widens to the width S_R
+ * itself certifies, w' = the smallest w' with S_R > U_out(w') (> w): the next
+ * region contains this one, so its score is at least S_R and the second pass
+ * always certifies.  With the flag NW_BAND_DOUBLING, w doubles instead (0
+ * becomes 1) and a pair may take more passes.  The full
  * grid is used directly once w >= min(m,n), once the band's height
  * 128 + |D| + 2w reaches fallback_frac of m, or when 2*gap >= c_d.  A first
  * half-width past the height limit (but below min(m,n)) is first lowered to
@@ -194,7 +203,8 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  * each pair's first half-width, e.g. the band model's prediction.  Optional
  * device outputs (NULL to skip): w_used[k] = final half-width (-1 = full
  * grid); status[k] = bit 0 certified on the first pass, bits 1..5 number of
- * doublings, bit 6 full grid, bit 7 certificate not applicable; cells[k] =
+ * widenings (passes - 1), bit 6 full grid, bit 7 certificate not applicable;
+ * cells[k] =
  * cells swept over all passes.  A pair with m == 0 or n == 0 reports
  * w_used -1, the full-grid bit and 0 cells; a pair over max_len reports
  * w_used -1, status 0 and 0 cells.

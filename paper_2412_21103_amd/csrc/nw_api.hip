@@ -319,23 +319,27 @@ __global__ void k_single_desc(int64_t* d64, int32_t* d32, int64_t b_off, int32_t
     }
 }
 
-int nw_align(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, nw_scoring sc,
-             uint32_t flags, int32_t* score, uint8_t* path, int64_t path_cap,
-             int64_t* path_len, void* ws, size_t ws_bytes, void* stream) {
+// Argument checks of nw_align (all before any work).
+static int check_align_args(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const nw_scoring& sc,
+                            uint32_t flags, const int32_t* score, const uint8_t* path, int64_t path_cap,
+                            const int64_t* path_len) {
     if (flags & ~NW_SCORE_ONLY) return NW_EINVAL;
     const bool dirs = !(flags & NW_SCORE_ONLY);
     int st = check_lengths(m, n, sc);
     if (st) return st;
-    if ((m > 0 && !a) || (n > 0 && !b) || !score || !ws) return NW_EINVAL;
+    if ((m > 0 && !a) || (n > 0 && !b) || !score) return NW_EINVAL;
     if (dirs && (!path_len || (m + n > 0 && !path))) return NW_EINVAL;
     if (dirs && path_cap < m + n) return NW_ENOSPC;
-    if ((st = check_scoring(sc, dirs))) return st;
-    DeviceInfo di;
-    if ((st = device_info(&di))) return st;
-    if (ws_bytes < single_workspace_bytes(m, n, dirs, di)) return NW_ENOSPC;
-    if (use_coop(m, n))
-        return launch_coop(a, m, b, n, sc, dirs, score, path, path_len, ws, ws_bytes,
-                           (hipStream_t)stream, di);
+    return check_scoring(sc, dirs);
+}
+
+// The single-pair path on a workspace of ws_bytes >= single_workspace_bytes:
+// the cooperative multi-wave engine from 512 columns, else the batch engine on
+// a one-pair descriptor written into the workspace.
+static int align_on(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const nw_scoring& sc, bool dirs,
+                    int32_t* score, uint8_t* path, int64_t* path_len, void* ws, size_t ws_bytes,
+                    hipStream_t s, const DeviceInfo& di) {
+    if (use_coop(m, n)) return launch_coop(a, m, b, n, sc, dirs, score, path, path_len, ws, ws_bytes, s, di);
     const int32_t ml = (int32_t)std::max<int64_t>(std::max(m, n), 1);
 
     uint8_t* base = (uint8_t*)ws;
@@ -347,7 +351,6 @@ int nw_align(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, nw_scorin
         pa = pb = (const uint8_t*)ws;
     }
     const int64_t b_off = (int64_t)((intptr_t)pb - (intptr_t)pa);
-    hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_single_desc, dim3(1), dim3(64), 0, s, d64, d32, b_off, (int32_t)m, (int32_t)n);
 
     BatchJob J{};
@@ -367,6 +370,19 @@ int nw_align(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, nw_scorin
     J.path_len = nullptr;
     J.path_len64 = dirs ? path_len : nullptr;
     return launch_batch(J, base + kDescBytes, ws_bytes - kDescBytes, s, di);
+}
+
+int nw_align(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, nw_scoring sc,
+             uint32_t flags, int32_t* score, uint8_t* path, int64_t path_cap,
+             int64_t* path_len, void* ws, size_t ws_bytes, void* stream) {
+    int st = check_align_args(a, m, b, n, sc, flags, score, path, path_cap, path_len);
+    if (st) return st;
+    if (!ws) return NW_EINVAL;
+    const bool dirs = !(flags & NW_SCORE_ONLY);
+    DeviceInfo di;
+    if ((st = device_info(&di))) return st;
+    if (ws_bytes < single_workspace_bytes(m, n, dirs, di)) return NW_ENOSPC;
+    return align_on(a, m, b, n, sc, dirs, score, path, path_len, ws, ws_bytes, (hipStream_t)stream, di);
 }
 
 // ------------------------------------------------------------------ batch
@@ -501,7 +517,8 @@ int nw_autotune(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const
 
 int nw_align_batch_banded_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags,
                                          size_t* bytes) {
-    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH))) return NW_EINVAL;
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH | NW_BAND_DOUBLING)))
+        return NW_EINVAL;
     DeviceInfo di;
     int st = device_info(&di);
     if (st) return st;
@@ -532,6 +549,7 @@ static int run_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
     J.path_off = path_off;
     J.path_len = dirs ? path_len : nullptr;
     J.banded = true;
+    J.band_doubling = (flags & NW_BAND_DOUBLING) != 0;
     J.w_init = w_init;
     J.w_default = w_default;
     J.frac_1024 = (int32_t)(fallback_frac * 1024.f);
@@ -547,7 +565,7 @@ static int check_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_of
                         uint32_t flags, float fallback_frac, const int32_t* scores, const uint8_t* paths,
                         const int64_t* path_off, const int32_t* path_len, const void* ws,
                         bool ws_stream_ok) {
-    if (npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH))) return NW_EINVAL;
+    if (npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH | NW_BAND_DOUBLING))) return NW_EINVAL;
     if ((flags & NW_GRAPH) && !ws_stream_ok) return NW_EINVAL;
     if (!(fallback_frac > 0.f) || fallback_frac > 64.f) return NW_EINVAL;
     const bool dirs = !(flags & NW_SCORE_ONLY);
@@ -696,7 +714,8 @@ static size_t learned_extra_bytes(int32_t npairs) {
 }
 
 int nw_align_batch_learned_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags, size_t* bytes) {
-    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH))) return NW_EINVAL;
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH | NW_BAND_DOUBLING)))
+        return NW_EINVAL;
     DeviceInfo di;
     int st = device_info(&di);
     if (st) return st;

@@ -32,6 +32,8 @@ struct KArgs {
     int32_t frac_1024;      // fall back to the full grid once the band is this fraction of m (x1024)
     int32_t cd;             // max(match, mismatch)
     int32_t band_ok;        // the certificate applies (2 gap < cd)
+    int32_t banded;         // order jobs by their first pass's band, not the full grid
+    int32_t band_doubling;  // widen a failed band by doubling (else to its certified width)
     int32_t* w_used;
     uint8_t* status;
     int64_t* cells;
@@ -126,12 +128,25 @@ __device__ __forceinline__ int cost_bucket(int64_t cost) {
     return 8 * e + (int)((cost >> (e - 3)) & 7);
 }
 
+// A job's cost for the largest-first order: the cells of its grid, or, for a
+// certified band, the cells of its first pass's band (rows per strip, ramp
+// included, times columns).
+template <bool ALLPAIRS>
+__device__ __forceinline__ int64_t job_cost(const KArgs& A, int q, const Pair& p) {
+    if (!ALLPAIRS && A.banded) {
+        const int w = max(0, A.w_init ? A.w_init[q] : A.w_default);
+        const int64_t dlt = p.n > p.m ? p.n - p.m : p.m - p.n;
+        return (int64_t)p.n * min((int64_t)p.m, 2 * kWave + dlt + 2 * (int64_t)w);
+    }
+    return (int64_t)p.m * p.n;
+}
+
 template <bool ALLPAIRS>
 __global__ void k_hist(KArgs A) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= A.njobs) return;
     Pair p = get_pair<ALLPAIRS>(A, q);
-    atomicAdd(&A.hist[cost_bucket((int64_t)p.m * p.n)], 1);
+    atomicAdd(&A.hist[cost_bucket(job_cost<ALLPAIRS>(A, q, p))], 1);
 }
 
 __global__ void k_scan(int32_t* hist, int32_t* cursor) {
@@ -149,7 +164,7 @@ __global__ void k_scatter(KArgs A) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= A.njobs) return;
     Pair p = get_pair<ALLPAIRS>(A, q);
-    int pos = atomicAdd(&A.cursor[cost_bucket((int64_t)p.m * p.n)], 1);
+    int pos = atomicAdd(&A.cursor[cost_bucket(job_cost<ALLPAIRS>(A, q, p))], 1);
     A.order[pos] = q;
 }
 
@@ -217,14 +232,16 @@ __device__ __forceinline__ int band_height(int C, int m, int n, int w) {
     return (int)min((int64_t)m, (int64_t)kWave * C + dlt + 2 * (int64_t)w);
 }
 
-// Sweep width for one pass (the full grid, or band(w)): the C in {2, 4, 8}
-// with the least modelled time, strips x (rows per strip + ramp) x step cost.
-__device__ __forceinline__ int pick_cols(const KArgs& A, int m, int n, bool full, int w) {
-    int best = 2;
+// Sweep width for one pass (the full grid, or band(w)): the C in {2, 4, 8},
+// at least c_min, with the least modelled time, strips x (rows per strip +
+// ramp) x step cost.
+__device__ __forceinline__ int pick_cols(const KArgs& A, int m, int n, bool full, int w, int c_min = 2) {
+    int best = 8;
     int64_t best_cost = INT64_MAX;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int C = 2 << c;
+        if (C < c_min) continue;
         const int64_t strips = (n + kWave * C - 1) / (kWave * C);
         const int height = full ? m : band_height(C, m, n, w);
         const int64_t cost = strips * (int64_t)(height + kWave) * A.step_cost[c];
@@ -302,9 +319,10 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
             int w = 0;
             int C = 8;
             if constexpr (BANDED) {
-                // certified band: double w until the region score beats the best
-                // score any path leaving band(w) can reach, or the band is so
-                // wide that the full grid is cheaper
+                // certified band: sweep band(w); if the region's score does not
+                // beat the best score any path leaving band(w) can reach, widen the
+                // band to the width that this score itself certifies, or take the
+                // full grid once the band is so wide that it is cheaper
                 w = max(0, A.w_init ? A.w_init[job] : A.w_default);
                 const int mn = min(m, n);
                 const int64_t dlt = n > m ? n - m : m - n;
@@ -316,21 +334,35 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                 const int64_t w_fb = fb_num >= 0 ? fb_num / 2048 : -1;
                 if (w < mn && w_fb >= 0 && w > w_fb) w = (int)w_fb;
                 int passes = 0;
+                int c_min = 2;
                 for (;;) {
                     full = !A.band_ok || w >= mn ||
                            (int64_t)(2 * kWave + dlt + 2 * (int64_t)w) * 1024 >= (int64_t)A.frac_1024 * m;
-                    C = uniform(pick_cols(A, m, n, full, w));
+                    C = uniform(pick_cols(A, m, n, full, w, c_min));
                     const int32_t v = fill_any<DIRS>(C, A, P.a, P.b, m, n, full, w, bnd, spare, dirs, lds, &G, &cells);
                     ++passes;
                     score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
                     if (full) break;
                     const int64_t u_out = (int64_t)A.cd * (mn - w - 1) + (int64_t)A.gap * (dlt + 2 * (int64_t)w + 2);
                     if ((int64_t)score > u_out) break;
-                    w = max(1, 2 * w);
+                    if (A.band_doubling) {
+                        w = max(1, 2 * w);
+                        continue;
+                    }
+                    // The failed score S_R <= U_out(w).  U_out falls by cd - 2 gap
+                    // per unit of w, so the smallest w' with S_R > U_out(w') is
+                    // num / (cd - 2 gap) + 1 > w.  The next region contains this
+                    // one (it is wider, and its sweep width is no narrower, so
+                    // its strips' row ranges cover these), so its score is at
+                    // least S_R and the next pass certifies.
+                    const int64_t num = (int64_t)A.cd * (mn - 1) + (int64_t)A.gap * (dlt + 2) - score;
+                    const int64_t den = (int64_t)A.cd - 2 * (int64_t)A.gap;
+                    w = (int)min((int64_t)mn, max((int64_t)w + 1, num / den + 1));
+                    c_min = C;
                 }
                 w_out = full ? -1 : w;
-                const int doublings = min(passes - 1, 31);
-                st_out = (uint32_t)((passes == 1 && !full ? 1 : 0) | (doublings << 1) | (full ? 0x40 : 0) |
+                const int widenings = min(passes - 1, 31);
+                st_out = (uint32_t)((passes == 1 && !full ? 1 : 0) | (widenings << 1) | (full ? 0x40 : 0) |
                                     (A.band_ok ? 0 : 0x80));
                 cells_out = cells;
             } else {
@@ -519,6 +551,8 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.frac_1024 = job.frac_1024;
     A.cd = std::max(job.sc.match, job.sc.mismatch);
     A.band_ok = 2 * job.sc.gap < A.cd ? 1 : 0;
+    A.banded = job.banded ? 1 : 0;
+    A.band_doubling = job.band_doubling ? 1 : 0;
     A.w_used = job.w_used;
     A.status = job.status;
     A.cells = job.cells;

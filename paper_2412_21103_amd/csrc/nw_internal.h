@@ -77,6 +77,7 @@ struct BatchJob {
     int32_t* matrix;     // all-pairs mode
     // certified band
     bool banded;
+    bool band_doubling;  // widen a failed band by doubling instead of to its certified width
     const int32_t* w_init;
     int32_t w_default;
     int32_t frac_1024;

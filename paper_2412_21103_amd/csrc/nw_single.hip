@@ -498,20 +498,35 @@ __global__ __launch_bounds__(kCoopThreads) void k_tb_emit(TbArgs T) {
 }
 
 // Workspace header words of the cooperative engine.
-constexpr int kHdrTicket = 0, kHdrErr = 16, kHdrSummary = 32, kHdrEpochCount = 48, kHdrEpoch = 49;
+constexpr int kHdrTicket = 0, kHdrErr = 16, kHdrSummary = 32, kHdrEpoch = 48;
+
+// The slot tag of the latest cooperative fill on this device.  A boundary
+// slot is taken as ready once it carries the reading call's tag, so no two
+// launches whose slots can meet in memory may share one: workspaces are
+// reused, and a fresh one can hold any earlier call's slots.  Tags therefore
+// only move forward on a device (modulo 2^32, ordered by signed difference):
+// each launch takes the later of the host's value for the call and the
+// previous tag, plus two.  Eager calls bring a new host value each; replays
+// of a captured graph bring the same host value again, and the device word
+// moves them on.
+__device__ uint32_t g_coop_tag;
 
 // Before each fill: clear the ticket, the failure flag and the traceback
-// summary, and advance the call's slot tag.  The tag is the host's value for
-// this call plus twice a counter kept in the workspace, so eager calls (a new
-// host value each) and replays of a captured graph (the same host value, the
-// counter moves on) both get a tag no earlier launch on this workspace used.
+// summary, and take the call's slot tag.
 __global__ void k_prep(int32_t* hdr, uint32_t host_epoch) {
     const int i = threadIdx.x;
-    if (i < kHdrEpochCount) hdr[i] = 0;
+    if (i < kHdrEpoch) hdr[i] = 0;
     if (i == 0) {
-        const uint32_t c = (uint32_t)hdr[kHdrEpochCount] + 1u;
-        hdr[kHdrEpochCount] = (int32_t)c;
-        hdr[kHdrEpoch] = (int32_t)((host_epoch + 2u * c) | 1u);
+        uint32_t prev = __hip_atomic_load(&g_coop_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t tag;
+        for (;;) {
+            const uint32_t base = ((int32_t)(host_epoch - prev) > 0) ? host_epoch : prev;
+            tag = (base + 2u) | 1u;  // odd: never the 0 of fresh memory
+            if (__hip_atomic_compare_exchange_strong(&g_coop_tag, &prev, tag, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+        hdr[kHdrEpoch] = (int32_t)tag;
     }
 }
 

@@ -1,5 +1,6 @@
 """Certified band: results bit-identical to the oracle (and to the full-grid
-batch) for every starting half-width, with doubling and fallback exercised."""
+batch) for every starting half-width, with both growth rules (to the width a
+failed pass's score certifies, and doubling) and the fallback exercised."""
 import numpy as np
 import pytest
 
@@ -23,13 +24,14 @@ def _dev(x, dt):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to("cuda")
 
 
-def run_band(pairs, w_init, scoring=P, w_default=0, frac=0.5):
+def run_band(pairs, w_init, scoring=P, w_default=0, frac=0.5, doubling=False):
     pool, ao, al, bo, bl = pack_pairs(pairs)
     ml = int(max(al.max(), bl.max()))
     wi = None if w_init is None else _dev(w_init, np.int32)
     s, paths, poff, plen, wu, st, cells = nwp.align_batch_banded(
         _dev(pool, np.uint8), _dev(ao, np.int64), _dev(al, np.int32), _dev(bo, np.int64),
-        _dev(bl, np.int32), ml, scoring, w_init=wi, w_default=w_default, fallback_frac=frac)
+        _dev(bl, np.int32), ml, scoring, w_init=wi, w_default=w_default, fallback_frac=frac,
+        doubling=doubling)
     torch.cuda.synchronize()
     paths = paths.cpu().numpy()
     poff = poff.cpu().numpy()
@@ -68,11 +70,30 @@ def test_band_with_certified_widths(small_band_batch):
 def test_band_doubling_from_zero(small_band_batch):
     pairs, ref = small_band_batch
     say("band: w_init = 0 (doubling)")
-    s, paths, wu, st, cells = run_band(pairs, None, w_default=0)
+    s, paths, wu, st, cells = run_band(pairs, None, w_default=0, doubling=True)
     check_equal(pairs, ref, s, paths, "w0=0")
     doublings = (st >> 1) & 31
     assert doublings.max() >= 2
     # the certified width is never below the closed-form minimum
+    for k in range(len(pairs)):
+        if wu[k] >= 0:
+            assert wu[k] >= band.w_cert(ref[k][0], len(pairs.a[k]), len(pairs.b[k]), P)
+
+
+@pytest.mark.parametrize("w0", [0, 5, 40])
+def test_band_widening_to_certified_width(small_band_batch, w0):
+    # A failed pass widens the band to the width its own score certifies, so
+    # the second pass always certifies (or is the full grid): no pair takes
+    # more than two passes, and the final width is at least w_cert.
+    pairs, ref = small_band_batch
+    say(f"band: w_init = {w0}, widening to the certified width")
+    s, paths, wu, st, cells = run_band(pairs, None, w_default=w0)
+    check_equal(pairs, ref, s, paths, f"w0={w0}")
+    widenings = (st >> 1) & 31
+    fullg = (st & 0x40) != 0
+    assert (widenings <= 1).all()
+    if w0 == 0:
+        assert (widenings[~fullg] == 1).sum() > 0
     for k in range(len(pairs)):
         if wu[k] >= 0:
             assert wu[k] >= band.w_cert(ref[k][0], len(pairs.a[k]), len(pairs.b[k]), P)

@@ -51,7 +51,7 @@ def test_trained_model_gain():
     say("band model: full grid, doubling from 0, learned")
     full = nwp.align_batch(*dte)
     s_full, p_full = _paths(full, len(test))
-    dbl = nwp.align_batch_banded(*dte, w_default=0)
+    dbl = nwp.align_batch_banded(*dte, w_default=0, doubling=True)
     lrn = nwp.align_batch_learned(*dte, mlp, 0.1)
     torch.cuda.synchronize()
     for tag, out in (("doubling", dbl), ("learned", lrn)):

@@ -1,5 +1,5 @@
-"""Device-fault reporting, forced from the host, and nw_align under graph
-capture.
+"""Device-fault reporting, forced from the host; nw_align under graph capture
+and on reused workspace memory.
 
 The waits between waves are bounded; nw_set_wait_limit makes them give up
 after a few polls so that the failure path runs without any real fault: every
@@ -10,7 +10,8 @@ each test ends, and a normal call afterwards must be exact again.
 Graph capture: nw_align on a pair wide enough for the multi-wave engine is
 captured once and replayed, with the input bytes changed in place between
 replays and eager work in between; every replay must equal the oracle on the
-bytes it read."""
+bytes it read.  Reused memory: stale slots and header words in a workspace
+never pass for a later call's data."""
 import numpy as np
 import pytest
 
@@ -130,3 +131,43 @@ def test_align_graph_replays_see_new_inputs():
         s2, p2, l2 = nwp.align(da, db, workspace=ws)
         torch.cuda.synchronize()
         assert _exact(a, b, s2, p2, l2), r
+
+
+def test_align_reused_workspace_with_stale_contents():
+    # A workspace is reused memory: boundary slots and header words that any
+    # earlier call left in it must never pass for this call's data.  One
+    # workspace, new input bytes every call, the header region overwritten
+    # between calls (random words, and words copied from the slot area, which
+    # hold earlier calls' tags), eager calls interleaved with graph replays.
+    m = 2500
+    rng = np.random.default_rng(11)
+    a0 = random_seq(rng, m)
+    b0 = mutate(rng, a0, 0.1)
+    n = len(b0)
+    da, db = dev_u8(a0), dev_u8(b0)
+    ws = torch.empty(nwp.align_workspace_size(m, n, 0), dtype=torch.uint8, device="cuda")
+    nwp.align(da, db, workspace=ws)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("faults: reused workspace with stale header and slots")
+    with torch.cuda.graph(g):
+        gs, gpath, gplen = nwp.align(da, db, workspace=ws)
+    hdr = ws[:256]
+    for r in range(12):
+        a = random_seq(rng, m)
+        b = mutate(rng, a, 0.02 + 0.02 * (r % 5))[:n]
+        if len(b) < n:
+            b = np.concatenate([b, random_seq(rng, n - len(b))])
+        da.copy_(dev_u8(a))
+        db.copy_(dev_u8(b))
+        if r % 3 == 0:
+            hdr.copy_(torch.from_numpy(rng.integers(0, 256, 256, dtype=np.uint8)).cuda())
+        elif r % 3 == 1:
+            hdr.copy_(ws[256 + 64 * r:512 + 64 * r])
+        if r % 2 == 0:
+            s, path, plen = nwp.align(da, db, workspace=ws)
+        else:
+            g.replay()
+            s, path, plen = gs, gpath, gplen
+        torch.cuda.synchronize()
+        assert _exact(a, b, s, path, plen), r

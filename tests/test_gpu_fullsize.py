@@ -1,8 +1,10 @@
 """Parity at the benchmark workloads' full sizes, in the launch configuration
-bench.py times: the 4096-pair batch (every pair against the oracle), the
-512-sequence all-pairs matrix (symmetry, diagonal, a 48-sequence block and
-random entries against the oracle) and the 8192-pair learned-band batch
-(identical to full DP on the device, a sample against the oracle)."""
+bench.py times, every output against the oracle: the 4096-pair batch (every
+score and path), the 512-sequence all-pairs matrix (all 130,816 entries,
+plus symmetry and the diagonal) and the 8192-pair learned-band batch (every
+score and every path byte, and identical to full DP on the device).  The
+oracle runs on all host threads in chunks, with a progress line after
+each."""
 import numpy as np
 import pytest
 
@@ -41,6 +43,13 @@ def test_batch_4096_every_pair():
     assert (s2 == s_ref).all()
 
 
+def _chunks(cost, parts):
+    """Split indices 0..len(cost)-1 into about `parts` runs of equal total cost."""
+    cum = np.cumsum(np.asarray(cost, np.float64))
+    edges = np.searchsorted(cum, np.linspace(0, cum[-1], parts + 1)[1:-1])
+    return np.split(np.arange(len(cost)), np.unique(edges + 1))
+
+
 def test_allpairs_512():
     seqs = config_allpairs()
     pool, off, lens = pack_seqs(seqs)
@@ -48,15 +57,14 @@ def test_allpairs_512():
     M = gpu_allpairs(pool, off, lens, int(lens.max()), P)
     assert (M == M.T).all()
     assert (np.diag(M) == lens.astype(np.int64) * P[0]).all()
-    say("full all-pairs: oracle on the first 48 sequences")
-    sub = seqs[:48]
-    sp, so, sl = pack_seqs(sub)
-    assert (M[:48, :48] == oracle.allpairs(sp, so, sl, P)).all()
-    rng = np.random.default_rng(1)
-    say("full all-pairs: oracle on 40 random entries")
-    for _ in range(40):
-        i, j = (int(x) for x in rng.integers(0, len(seqs), 2))
-        assert M[i, j] == oracle.score(seqs[i], seqs[j], P), (i, j)
+    iu, ju = np.triu_indices(len(seqs), 1)
+    cost = lens[iu].astype(np.float64) * lens[ju]
+    for c, sel in enumerate(_chunks(cost, 8)):
+        s_ref, _ = oracle.align_batch(pool, off[iu[sel]], lens[iu[sel]], off[ju[sel]], lens[ju[sel]], P,
+                                      with_paths=False)
+        bad = np.nonzero(M[iu[sel], ju[sel]] != s_ref)[0]
+        assert len(bad) == 0, [(int(iu[sel][k]), int(ju[sel][k])) for k in bad[:8]]
+        say(f"full all-pairs: oracle chunk {c + 1}/8 equal ({len(sel)} entries)")
 
 
 def test_learned_band_8192():
@@ -83,15 +91,15 @@ def test_learned_band_8192():
     assert torch.equal(p[idx], p_ref[idx])
     full_cells = float((d[2].double() * d[4].double()).sum())
     assert float(cells.sum()) < 0.6 * full_cells
-    # a sample against the oracle: four random pairs and the two largest
+    # every pair against the oracle: score, path length and every path byte
     s_h, p_h, o_h, l_h = s.cpu().numpy(), p.cpu().numpy(), poff.cpu().numpy(), plen.cpu().numpy()
-    rng = np.random.default_rng(2)
-    cost = np.array([len(a) * len(b) for a, b in zip(test.a, test.b)])
-    sample = list(rng.choice(len(test), 4, replace=False)) + list(np.argsort(cost)[-2:])
-    say(f"learned band: oracle on pairs {sample}")
     pool, ao, al, bo, bl = pack_pairs(test)
-    sel = np.array(sample)
-    ref_s, ref_p = oracle.align_batch(pool, ao[sel], al[sel], bo[sel], bl[sel], P)
-    for q, k in enumerate(sample):
-        assert s_h[k] == ref_s[q], k
-        assert p_h[o_h[k]:o_h[k] + l_h[k]].tolist() == ref_p[q].tolist(), k
+    cost = al.astype(np.float64) * bl
+    parts = _chunks(cost, 8)
+    for c, sel in enumerate(parts):
+        ref_s, ref_p = oracle.align_batch(pool, ao[sel], al[sel], bo[sel], bl[sel], P)
+        for q, k in enumerate(sel):
+            assert s_h[k] == ref_s[q], (k, s_h[k], ref_s[q])
+            assert l_h[k] == len(ref_p[q]), k
+            assert np.array_equal(p_h[o_h[k]:o_h[k] + l_h[k]], ref_p[q]), k
+        say(f"learned band: oracle chunk {c + 1}/{len(parts)} equal ({len(sel)} pairs)")
