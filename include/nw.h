@@ -155,6 +155,33 @@ int nw_align(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n, nw_scorin
              int64_t *path_len, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * nw_align without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, outputs, checks and errors as
+ * nw_align, minus ws/ws_bytes: the workspace is a fixed array of
+ * NW_SCRATCH_BYTES in the library's device code, one per device, allocated
+ * when the library is loaded on that device and held until the process ends.
+ * The call makes no hipMalloc, hipFree or other allocating call (nw_init,
+ * called once beforehand, does the library's own set-up; without it, device
+ * faults are not reported through the fault word).  A pair whose nw_align
+ * workspace exceeds NW_SCRATCH_BYTES returns NW_ENOSPC before any work is
+ * queued; nw_align_noalloc_fits(m, n, flags) answers the same question
+ * (NW_OK or NW_ENOSPC) without queueing anything.  With 64 MiB, full
+ * alignments with paths fit up to about 14,000 x 14,000.
+ * Every call on a device uses the same array and leaves its contents behind
+ * (each call clears what it needs cleared): calls that overlap in time on one
+ * device -- on different streams, or from different host threads -- race and
+ * give wrong results; serialise them on one stream.
+ * ------------------------------------------------------------------------ */
+#define NW_SCRATCH_BYTES ((size_t)64 << 20)
+
+int nw_align_noalloc(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n, nw_scoring sc,
+                     uint32_t flags, int32_t *score, uint8_t *path, int64_t path_cap,
+                     int64_t *path_len, void *stream);
+
+int nw_align_noalloc_fits(int64_t m, int64_t n, uint32_t flags);
+
+/* ------------------------------------------------------------------------
  * Many independent pairs in one persistent launch (the data-parallel form of
  * the paper's multiple-alignment workload, Sec. 3.2).
  *

@@ -21,7 +21,7 @@ __all__ = [
     "profile_end", "align_batch_banded", "banded_workspace_size", "Mlp", "MLP_INPUTS",
     "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_widths", "band_labels", "mlp_train_step",
     "mlp_train_epoch", "align_batch_learned", "learned_workspace_size", "autotune", "init", "sync",
-    "set_wait_limit",
+    "set_wait_limit", "align_noalloc", "align_noalloc_fits",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -76,6 +76,8 @@ def lib():
         L.nw_version.restype = ctypes.c_int
         L.nw_align_workspace_size.argtypes = [_i64, _i64, _u32, ctypes.POINTER(_sz)]
         L.nw_align.argtypes = [_vp, _i64, _vp, _i64, Scoring, _u32, _vp, _vp, _i64, _vp, _vp, _sz, _vp]
+        L.nw_align_noalloc.argtypes = [_vp, _i64, _vp, _i64, Scoring, _u32, _vp, _vp, _i64, _vp, _vp]
+        L.nw_align_noalloc_fits.argtypes = [_i64, _i64, _u32]
         L.nw_align_batch_workspace_size.argtypes = [_i32, _i32, _u32, ctypes.POINTER(_sz)]
         L.nw_align_batch.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _u32, _vp, _vp,
                                      _vp, _vp, _vp, _sz, _vp]
@@ -191,6 +193,26 @@ def align(a: torch.Tensor, b: torch.Tensor, scoring=PAPER_SCORING, score_only: b
                         _stream(stream))
     _check(st, "nw_align")
     return score, path, plen
+
+
+def align_noalloc(a: torch.Tensor, b: torch.Tensor, score: torch.Tensor, path: torch.Tensor | None = None,
+                  path_len: torch.Tensor | None = None, scoring=PAPER_SCORING, stream=None):
+    """nw_align on the library's own fixed device scratch: the caller passes
+    the outputs (int32[1] score; uint8[>= m+n] path and int64[1] path_len, or
+    None for the score only) and the call allocates nothing."""
+    m, n = int(a.numel()), int(b.numel())
+    flags = SCORE_ONLY if path is None else 0
+    cap = int(path.numel()) if path is not None else 0
+    st = lib().nw_align_noalloc(_ptr(a), m, _ptr(b), n, _sc(scoring), flags, _ptr(score), _ptr(path), cap,
+                                _ptr(path_len), _stream(stream))
+    _check(st, "nw_align_noalloc")
+
+
+def align_noalloc_fits(m: int, n: int, score_only: bool = False) -> bool:
+    st = lib().nw_align_noalloc_fits(int(m), int(n), SCORE_ONLY if score_only else 0)
+    if st not in (NW_OK, -3):
+        raise NWError(st, "nw_align_noalloc_fits")
+    return st == NW_OK
 
 
 def align_batch(pool: torch.Tensor, a_off: torch.Tensor, a_len: torch.Tensor, b_off: torch.Tensor,

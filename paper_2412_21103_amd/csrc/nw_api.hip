@@ -63,7 +63,7 @@ int take_fault(int device) {
     return 1;
 }
 
-int device_info(DeviceInfo* out) {
+int device_info(DeviceInfo* out, bool may_allocate) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return NW_EDEVICE;
     hipDeviceProp_t prop;
@@ -71,7 +71,7 @@ int device_info(DeviceInfo* out) {
     out->device = dev;
     out->cus = prop.multiProcessorCount;
     out->supported = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-    init_fault_words();
+    if (may_allocate) init_fault_words();
     FaultWords& F = fault_words();
     out->fault = (F.dev && dev < kMaxFaultDevices) ? F.dev + dev : nullptr;
     out->spin_limit = g_spin_limit.load();
@@ -210,6 +210,39 @@ static uint64_t wsc(const nw_scoring& sc) {
     return ((uint64_t)(uint32_t)sc.match << 32) ^ ((uint64_t)(uint32_t)sc.mismatch << 16) ^ (uint32_t)sc.gap;
 }
 
+// ---- nw_align without a workspace argument and without allocation ----
+//
+// The workspace of nw_align_noalloc is this file-scope array: one copy per
+// device, allocated when the library's code object is loaded on that device
+// and held until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is a stand-in, not a device address): the
+// device address comes from hipGetSymbolAddress, once per device, and only
+// that address is used.
+static __device__ __align__(256) uint8_t scratch[NW_SCRATCH_BYTES];
+
+struct ScratchAddrs {
+    std::mutex mu;
+    void* ptr[kMaxFaultDevices] = {};
+};
+static ScratchAddrs& scratch_addrs() {
+    static ScratchAddrs s;
+    return s;
+}
+
+// Device address of this device's scratch array (resolved on first use, with
+// the device current), or nullptr if it cannot be resolved.
+static void* scratch_on(int device) {
+    if (device < 0 || device >= kMaxFaultDevices) return nullptr;
+    ScratchAddrs& S = scratch_addrs();
+    std::lock_guard<std::mutex> lock(S.mu);
+    if (!S.ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        S.ptr[device] = p;
+    }
+    return S.ptr[device];
+}
+
 }  // namespace nw
 
 using namespace nw;
@@ -221,7 +254,7 @@ const char* nw_strerror(int status) {
         case NW_OK: return "success";
         case NW_EINVAL: return "invalid argument (null pointer, negative length or count, bad flag)";
         case NW_ERANGE: return "lengths or scoring constants exceed the overflow guard";
-        case NW_ENOSPC: return "path capacity or workspace too small";
+        case NW_ENOSPC: return "path capacity or workspace too small (or the pair exceeds nw_align_noalloc's scratch)";
         case NW_EDEVICE: return "HIP error while queueing work, or a device fault reported by earlier work";
         case NW_ENOTSUP: return "current device is not a gfx950 GPU";
         default: return "unknown status";
@@ -235,6 +268,7 @@ int nw_init(void) {
     const int st = device_info(&di);
     if (st == NW_ENOTSUP) return st;
     if (!fault_words().host) return NW_EDEVICE;
+    if (!scratch_on(di.device)) return NW_EDEVICE;
     return st;
 }
 
@@ -319,7 +353,7 @@ __global__ void k_single_desc(int64_t* d64, int32_t* d32, int64_t b_off, int32_t
     }
 }
 
-// Argument checks of nw_align (all before any work).
+// Argument checks of nw_align and nw_align_noalloc (all before any work).
 static int check_align_args(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const nw_scoring& sc,
                             uint32_t flags, const int32_t* score, const uint8_t* path, int64_t path_cap,
                             const int64_t* path_len) {
@@ -383,6 +417,30 @@ int nw_align(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, nw_scorin
     if ((st = device_info(&di))) return st;
     if (ws_bytes < single_workspace_bytes(m, n, dirs, di)) return NW_ENOSPC;
     return align_on(a, m, b, n, sc, dirs, score, path, path_len, ws, ws_bytes, (hipStream_t)stream, di);
+}
+
+int nw_align_noalloc(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, nw_scoring sc,
+                     uint32_t flags, int32_t* score, uint8_t* path, int64_t path_cap,
+                     int64_t* path_len, void* stream) {
+    int st = check_align_args(a, m, b, n, sc, flags, score, path, path_cap, path_len);
+    if (st) return st;
+    const bool dirs = !(flags & NW_SCORE_ONLY);
+    DeviceInfo di;
+    if ((st = device_info(&di, false))) return st;
+    if (single_workspace_bytes(m, n, dirs, di) > NW_SCRATCH_BYTES) return NW_ENOSPC;
+    void* ws = scratch_on(di.device);
+    if (!ws) return NW_EDEVICE;
+    return align_on(a, m, b, n, sc, dirs, score, path, path_len, ws, NW_SCRATCH_BYTES, (hipStream_t)stream, di);
+}
+
+int nw_align_noalloc_fits(int64_t m, int64_t n, uint32_t flags) {
+    if (flags & ~NW_SCORE_ONLY) return NW_EINVAL;
+    if (m < 0 || n < 0) return NW_EINVAL;
+    if (m > INT32_MAX / 4 || n > INT32_MAX / 4) return NW_ERANGE;
+    DeviceInfo di;
+    int st = device_info(&di, false);
+    if (st) return st;
+    return single_workspace_bytes(m, n, !(flags & NW_SCORE_ONLY), di) <= NW_SCRATCH_BYTES ? NW_OK : NW_ENOSPC;
 }
 
 // ------------------------------------------------------------------ batch

@@ -28,7 +28,10 @@ struct DeviceInfo {
     uint32_t* fault;     // device view of this device's fault word (nullptr before nw_init)
     int32_t spin_limit;  // polls before a boundary wait gives up
 };
-int device_info(DeviceInfo* out);
+// Fills *out for the current device.  With may_allocate (the default) the
+// pinned fault words are set up on first use; without, a library that was
+// never initialised reports no faults (fault = nullptr).
+int device_info(DeviceInfo* out, bool may_allocate = true);
 
 // Default polls before a boundary wait gives up: far beyond any legitimate
 // wait (the last strip of a long pair waits for the whole pipeline to reach
