@@ -5,13 +5,16 @@ Default workload (the metric's configuration): the learned-band batch --
 8192 pairs of lengths 1,000..20,000 at divergence 1..30% and indel fraction
 5..50%, seeded; paper scoring +1/-1/-1; scores and tie-break paths.  One step
 is one nw_align_batch_learned call (k-mer features, network, half-widths,
-certified banded fill with doubling and fallback, traceback) on inputs
-already resident in HBM.  The band model is trained in the same run on 4096
-pairs from disjoint seeds, with labels from the full-DP method.  Beside it on
-the same GPU and inputs: full DP (nw_align_batch) and the certified band with
-doubling from the best constant starting half-width (the method without the
-network), every score and path byte compared with full DP on the device, and
-the CPU oracle on a bounded sample of the pairs.
+certified banded fill, widening a failed band to the width its score
+certifies, traceback) on inputs already resident in HBM.  The band model is
+trained in the same run on 4096 pairs from disjoint seeds, on the excursion
+of the full-DP method's own paths beyond the straight band.  Beside it on
+the same GPU and inputs: full DP (nw_align_batch); the certified band from
+the best constant starting half-width (the method without the network,
+chosen on the training pairs by wall time); and both again under the
+doubling rule (the network then trained on the certified width).  Every
+score and path byte is compared with full DP on the device, and the CPU
+oracle runs on a bounded sample of the pairs.
 
 Prints one JSON line: effective GCUPS of the learned band (full-equivalent
 m*n cells per second of wall time) as `value`, the banded kernel's roofline
@@ -166,14 +169,17 @@ def bench_band_batch(args):
     test, train = Batch(test_pairs), Batch(train_pairs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x, _, _, target = band_model.features_and_labels(*train.d, train.max_len)
+    x, _, _, t_path = band_model.features_and_labels(*train.d, train.max_len, label="path")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    mlp, hist = band_model.train(x, target, epochs=200, batch=256, lr=3e-3, tau=0.9, seed=1)
+    mlp, hist = band_model.train(x, t_path, epochs=200, batch=256, lr=3e-3, tau=0.9, seed=1)
     t2 = time.perf_counter()
+    # the network the doubling rule needs: trained on the certified width
+    _, _, _, t_cert = band_model.features_and_labels(*train.d, train.max_len, label="cert")
+    mlp_cert, hist_cert = band_model.train(x, t_cert, epochs=200, batch=256, lr=3e-3, tau=0.9, seed=1)
     print(f"bench: labels {t1 - t0:.2f} s, training {t2 - t1:.2f} s, loss {hist[0]:.3f} -> {hist[-1]:.4f}",
           file=sys.stderr, flush=True)
-    del x, target
+    del x, t_path, t_cert
 
     L = nwp.lib()
     sc = nwp.Scoring(*nwp.PAPER_SCORING)
@@ -181,7 +187,8 @@ def bench_band_batch(args):
     vp = ctypes.c_void_p
     ptr = lambda x: vp(x.data_ptr()) if x is not None else vp(0)
     frac = 0.5
-    margin = 0.1
+    margin = 0.5       # on the path excursion (widening)
+    margin_cert = 0.1  # on the certified width (doubling)
     ws_bytes = max(nwp.learned_workspace_size(test.n, test.max_len), nwp.batch_workspace_size(test.n, test.max_len))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
 
@@ -191,17 +198,19 @@ def bench_band_batch(args):
         if st != 0:
             raise nwp.NWError(st, "nw_align_batch")
 
-    def const(B, w0):
-        st = L.nw_align_batch_banded(B.n, *[ptr(v) for v in B.d], B.max_len, sc, 0, vp(0), int(w0),
+    def const(B, w0, flags=0):
+        st = L.nw_align_batch_banded(B.n, *[ptr(v) for v in B.d], B.max_len, sc, flags, vp(0), int(w0),
                                      ctypes.c_float(frac), ptr(B.scores), ptr(B.paths), ptr(B.poff), ptr(B.plen),
                                      ptr(B.w_used), ptr(B.status), ptr(B.swept), ptr(ws), ws_bytes,
                                      vp(stream.cuda_stream))
         if st != 0:
             raise nwp.NWError(st, "nw_align_batch_banded")
 
-    def learned(B):
-        st = L.nw_align_batch_learned(B.n, *[ptr(v) for v in B.d], B.max_len, sc, 0, ctypes.byref(mlp.state),
-                                      ctypes.c_float(margin), ctypes.c_float(frac), ptr(B.scores), ptr(B.paths),
+    def learned(B, net=None, mg=None, flags=0):
+        net = mlp if net is None else net
+        mg = margin if mg is None else mg
+        st = L.nw_align_batch_learned(B.n, *[ptr(v) for v in B.d], B.max_len, sc, flags, ctypes.byref(net.state),
+                                      ctypes.c_float(mg), ctypes.c_float(frac), ptr(B.scores), ptr(B.paths),
                                       ptr(B.poff), ptr(B.plen), ptr(B.w_used), ptr(B.status), ptr(B.swept),
                                       ptr(ws), ws_bytes, vp(stream.cuda_stream))
         if st != 0:
@@ -211,11 +220,13 @@ def bench_band_batch(args):
 
     # arm (ii): the best constant starting half-width on the training pairs, by wall time
     print("bench: choosing the constant starting half-width on the training pairs", file=sys.stderr, flush=True)
-    w0_ms = {}
+    DBL = 0x4  # NW_BAND_DOUBLING
+    w0_ms, w0_ms_dbl = {}, {}
     for w0 in [0, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]:
-        wall, ms, _ = _events_timed(lambda: const(train, w0), 1, 2, sync, profile=False)
-        w0_ms[w0] = min(ms)
+        w0_ms[w0] = min(_events_timed(lambda: const(train, w0), 1, 2, sync, profile=False)[1])
+        w0_ms_dbl[w0] = min(_events_timed(lambda: const(train, w0, DBL), 1, 2, sync, profile=False)[1])
     w0_best = min(w0_ms, key=w0_ms.get)
+    w0_best_dbl = min(w0_ms_dbl, key=w0_ms_dbl.get)
 
     def snapshot(B):
         return (B.scores.clone(), B.paths.clone(), B.plen.clone(), B.w_used.clone(), B.status.clone(),
@@ -241,13 +252,19 @@ def bench_band_batch(args):
     print("bench: arm (i) full DP", file=sys.stderr, flush=True)
     wall_f, ms_f, prof_f = _events_timed(lambda: full(test), W, K, sync)
     ref = snapshot(test)
-    print(f"bench: arm (ii) certified band from w0 = {w0_best}", file=sys.stderr, flush=True)
+    print(f"bench: arm (ii) certified band from the constant w0 = {w0_best}", file=sys.stderr, flush=True)
     wall_c, ms_c, prof_c = _events_timed(lambda: const(test, w0_best), W, K, sync)
     out_c = snapshot(test)
+    print("bench: doubling arms", file=sys.stderr, flush=True)
+    wall_cd, ms_cd, prof_cd = _events_timed(lambda: const(test, w0_best_dbl, DBL), W, max(K // 2, 1), sync)
+    out_cd = snapshot(test)
+    wall_ld, ms_ld, prof_ld = _events_timed(lambda: learned(test, mlp_cert, margin_cert, DBL), W, max(K // 2, 1), sync)
+    out_ld = snapshot(test)
     print("bench: arm (iii) learned band", file=sys.stderr, flush=True)
     wall_l, ms_l, prof_l = _events_timed(lambda: learned(test), W, K, sync)
     out_l = snapshot(test)
     exact_c, exact_l = same(out_c, ref), same(out_l, ref)
+    exact_dbl = same(out_cd, ref) and same(out_ld, ref)
 
     def arm(name, wall, ms, prof, out, kernel):
         d = {"wall_ms_per_step": round(wall, 3), **_stats(ms),
@@ -258,7 +275,7 @@ def bench_band_batch(args):
             d.update({"computed_gcups": round(swept / (wall * 1e-3) / 1e9, 1),
                       "cells_swept_frac": round(swept / test.cells, 4),
                       "certified_first_pass": round(float(np.mean(st & 1)), 4),
-                      "doublings_mean": round(float(np.mean((st >> 1) & 31)), 3),
+                      "extra_passes_mean": round(float(np.mean((st >> 1) & 31)), 3),
                       "full_grid_frac": round(float(np.mean((st & 0x40) != 0)), 4)})
         k = prof.get(kernel)
         if k:
@@ -271,6 +288,10 @@ def bench_band_batch(args):
     res_learned = arm("learned", wall_l, ms_l, prof_l, out_l, "nw_batch_banded")
     res_const["w0"] = w0_best
     res_const["w0_search_train_ms"] = {str(k): round(v, 2) for k, v in w0_ms.items()}
+    res_dbl_const = arm("dbl_const", wall_cd, ms_cd, prof_cd, out_cd, "nw_batch_banded")
+    res_dbl_const["w0"] = w0_best_dbl
+    res_dbl_const["w0_search_train_ms"] = {str(k): round(v, 2) for k, v in w0_ms_dbl.items()}
+    res_dbl_learned = arm("dbl_learned", wall_ld, ms_ld, prof_ld, out_ld, "nw_batch_banded")
 
     # roofline of the banded kernel in the learned arm: computed cells per launch
     kb = prof_l.get("nw_batch_banded")
@@ -306,13 +327,20 @@ def bench_band_batch(args):
 
     config = {"workload": f"band_batch_{npairs}", "pairs": npairs, "full_equivalent_cells": test.cells,
               "scoring": list(nwp.PAPER_SCORING), "traceback": True, "margin": margin, "fallback_frac": frac,
+              "growth": "widen a failed band to the width its score certifies",
+              "label": "w_path (excursion of the full-DP path beyond the straight band)",
               "learned_band": res_learned, "full_dp": res_full, "constant_band": res_const,
               "speedup_learned_vs_full_dp": round(wall_f / wall_l, 3),
               "speedup_learned_vs_constant_band": round(wall_c / wall_l, 3),
+              "doubling": {"label": "w_cert", "margin": margin_cert, "learned_band": res_dbl_learned,
+                           "constant_band": res_dbl_const,
+                           "speedup_learned_vs_constant_band": round(wall_cd / wall_ld, 3),
+                           "bit_exact_vs_full_dp": exact_dbl},
               "bit_exact_learned_vs_full_dp": exact_l, "bit_exact_constant_vs_full_dp": exact_c,
               "bit_exact_vs_oracle_sample": exact_oracle,
               "train_pairs": ntrain, "train_s": round(t2 - t1, 3), "label_dp_s": round(t1 - t0, 3),
-              "train_loss": [round(hist[0], 4), round(hist[-1], 4)]}
+              "train_loss": [round(hist[0], 4), round(hist[-1], 4)],
+              "train_loss_cert": [round(hist_cert[0], 4), round(hist_cert[-1], 4)]}
     return common_fields(args, test.cells / (wall_l * 1e-3) / 1e9, wall_l, config, roof, cpu)
 
 

@@ -217,10 +217,15 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  * path equal the full grid's.  Otherwise the band widens to the width S_R
  * itself certifies, w' = the smallest w' with S_R > U_out(w') (> w): the next
  * region contains this one, so its score is at least S_R and the second pass
- * always certifies.  With the flag NW_BAND_DOUBLING, w doubles instead (0
- * becomes 1) and a pair may take more passes.  The full
- * grid is used directly once w >= min(m,n), once the band's height
- * 128 + |D| + 2w reaches fallback_frac of m, or when 2*gap >= c_d.  A first
+ * always certifies.  Because the first pass serves mostly to find S_R, it
+ * runs score-only (no directions); if it certifies after all, the same band
+ * is swept again with directions.  With the flag NW_BAND_DOUBLING, w doubles
+ * instead (0 becomes 1), every pass records directions, and a pair may take
+ * more passes.  The full
+ * grid is used directly once w >= min(m,n), when 2*gap >= c_d, or once the
+ * band's height 128 + |D| + 2w reaches fallback_frac of m -- for a first pass
+ * or any doubled one; a widened pass, which is certain to certify, takes the
+ * full grid only once that height reaches m.  A first
  * half-width past the height limit (but below min(m,n)) is first lowered to
  * the widest band under the limit, so a pair reaches the full grid only after
  * a band has failed.  Each pass sweeps 128, 256 or 512 columns per wave,
@@ -230,7 +235,7 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  * each pair's first half-width, e.g. the band model's prediction.  Optional
  * device outputs (NULL to skip): w_used[k] = final half-width (-1 = full
  * grid); status[k] = bit 0 certified on the first pass, bits 1..5 number of
- * widenings (passes - 1), bit 6 full grid, bit 7 certificate not applicable;
+ * passes after the first, bit 6 full grid, bit 7 certificate not applicable;
  * cells[k] =
  * cells swept over all passes.  A pair with m == 0 or n == 0 reports
  * w_used -1, the full-grid bit and 0 cells; a pair over max_len reports
@@ -400,6 +405,19 @@ int nw_mlp_widths(int32_t npairs, const float *yhat, const int32_t *a_len, const
 int nw_band_labels(int32_t npairs, const int32_t *scores, const int32_t *a_len,
                    const int32_t *b_len, nw_scoring sc, int32_t *w_cert, float *target,
                    void *stream);
+
+/* Training labels from full-grid paths (the network's target: the maximum
+ * diagonal offset of the optimal path, measured beyond the straight band).
+ * paths, path_off, path_len (device) as nw_align_batch returns them, with
+ * a_len/b_len of the same pairs.  w_path[k] (device int32, may be NULL) =
+ * the largest excursion of path k outside the corridor [min(0,D), max(0,D)],
+ * D = b_len[k] - a_len[k]: the half-width of the smallest band(w) that holds
+ * the path (Sec. 5's aim: a band that keeps the optimal alignment);
+ * target[k] = log1pf(w_path[k]) (device float32, may be NULL).  A pair with
+ * path_len[k] <= 0 gets 0. */
+int nw_path_labels(int32_t npairs, const uint8_t *paths, const int64_t *path_off,
+                   const int32_t *path_len, const int32_t *a_len, const int32_t *b_len,
+                   int32_t *w_path, float *target, void *stream);
 
 /* Workspace for nw_mlp_train_step / nw_mlp_train_epoch at minibatch size
  * `batch`. */

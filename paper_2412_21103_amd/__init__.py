@@ -19,7 +19,7 @@ __all__ = [
     "align_workspace_size", "batch_workspace_size", "allpairs_workspace_size",
     "declared_functions", "MOVE_D", "MOVE_U", "MOVE_L", "SCORE_ONLY", "GRAPH", "profile_begin",
     "profile_end", "align_batch_banded", "banded_workspace_size", "Mlp", "MLP_INPUTS",
-    "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_widths", "band_labels", "mlp_train_step",
+    "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_widths", "band_labels", "path_labels", "mlp_train_step",
     "mlp_train_epoch", "align_batch_learned", "learned_workspace_size", "autotune", "init", "sync",
     "set_wait_limit", "align_noalloc", "align_noalloc_fits",
 ]
@@ -92,6 +92,7 @@ def lib():
         L.nw_mlp_forward.argtypes = [_pm, _i32, _vp, _vp, _vp]
         L.nw_mlp_widths.argtypes = [_i32, _vp, _vp, _vp, _f, _vp, _vp]
         L.nw_band_labels.argtypes = [_i32, _vp, _vp, _vp, Scoring, _vp, _vp, _vp]
+        L.nw_path_labels.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.nw_mlp_train_workspace_size.argtypes = [_i32, ctypes.POINTER(_sz)]
         L.nw_mlp_train_step.argtypes = [_pm, _i32, _vp, _vp, _vp, _f, _f, _vp, _vp, _vp, _sz, _vp]
         L.nw_mlp_train_epoch.argtypes = [_pm, _i32, _vp, _vp, _vp, _i32, _f, _f, _vp, _vp, _sz, _vp]
@@ -360,6 +361,18 @@ def band_labels(scores, a_len, b_len, scoring=PAPER_SCORING, stream=None):
     t = torch.empty(n, dtype=torch.float32, device=dev)
     _check(lib().nw_band_labels(n, _ptr(scores), _ptr(a_len), _ptr(b_len), _sc(scoring), _ptr(w), _ptr(t),
                                 _stream(stream)), "nw_band_labels")
+    return w, t
+
+
+def path_labels(paths, path_off, path_len, a_len, b_len, stream=None):
+    """(w_path int32, target float32 = log1p(w_path)) device tensors from
+    full-grid paths (as align_batch returns them)."""
+    n = int(a_len.numel())
+    dev = _dev()
+    w = torch.empty(n, dtype=torch.int32, device=dev)
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    _check(lib().nw_path_labels(n, _ptr(paths), _ptr(path_off), _ptr(path_len), _ptr(a_len), _ptr(b_len),
+                                _ptr(w), _ptr(t), _stream(stream)), "nw_path_labels")
     return w, t
 
 

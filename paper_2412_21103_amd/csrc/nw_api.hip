@@ -722,6 +722,18 @@ int nw_band_labels(int32_t npairs, const int32_t* scores, const int32_t* a_len, 
     return launch_band_labels(npairs, scores, a_len, b_len, cd, sc.gap, w_cert, target, (hipStream_t)stream);
 }
 
+int nw_path_labels(int32_t npairs, const uint8_t* paths, const int64_t* path_off, const int32_t* path_len,
+                   const int32_t* a_len, const int32_t* b_len, int32_t* w_path, float* target, void* stream) {
+    if (npairs < 0) return NW_EINVAL;
+    if (npairs == 0) return NW_OK;
+    if (!paths || !path_off || !path_len || !a_len || !b_len || (!w_path && !target)) return NW_EINVAL;
+    DeviceInfo di;
+    int st = device_info(&di);
+    if (st) return st;
+    return launch_path_labels(npairs, paths, path_off, path_len, a_len, b_len, w_path, target,
+                              (hipStream_t)stream);
+}
+
 int nw_mlp_train_workspace_size(int32_t batch, size_t* bytes) {
     if (!bytes || batch < 1) return NW_EINVAL;
     *bytes = mlp_train_workspace_bytes(batch);

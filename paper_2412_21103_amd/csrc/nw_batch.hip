@@ -32,7 +32,6 @@ struct KArgs {
     int32_t frac_1024;      // fall back to the full grid once the band is this fraction of m (x1024)
     int32_t cd;             // max(match, mismatch)
     int32_t band_ok;        // the certificate applies (2 gap < cd)
-    int32_t banded;         // order jobs by their first pass's band, not the full grid
     int32_t band_doubling;  // widen a failed band by doubling (else to its certified width)
     int32_t* w_used;
     uint8_t* status;
@@ -44,6 +43,7 @@ struct KArgs {
     const int32_t* b_len;
     int32_t max_len;
     int32_t kdm, kdx, gap;
+    int32_t kdm_w, kdx_w;   // the W-domain (score-only) terms, for score-only passes of a sweep with directions
     // per-step cost of a sweep with C = 2, 4, 8 columns per lane (relative
     // units); the engine picks, per pair and pass, the width whose strips x
     // (rows + ramp) x step cost is smallest
@@ -128,25 +128,12 @@ __device__ __forceinline__ int cost_bucket(int64_t cost) {
     return 8 * e + (int)((cost >> (e - 3)) & 7);
 }
 
-// A job's cost for the largest-first order: the cells of its grid, or, for a
-// certified band, the cells of its first pass's band (rows per strip, ramp
-// included, times columns).
-template <bool ALLPAIRS>
-__device__ __forceinline__ int64_t job_cost(const KArgs& A, int q, const Pair& p) {
-    if (!ALLPAIRS && A.banded) {
-        const int w = max(0, A.w_init ? A.w_init[q] : A.w_default);
-        const int64_t dlt = p.n > p.m ? p.n - p.m : p.m - p.n;
-        return (int64_t)p.n * min((int64_t)p.m, 2 * kWave + dlt + 2 * (int64_t)w);
-    }
-    return (int64_t)p.m * p.n;
-}
-
 template <bool ALLPAIRS>
 __global__ void k_hist(KArgs A) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= A.njobs) return;
     Pair p = get_pair<ALLPAIRS>(A, q);
-    atomicAdd(&A.hist[cost_bucket(job_cost<ALLPAIRS>(A, q, p))], 1);
+    atomicAdd(&A.hist[cost_bucket((int64_t)p.m * p.n)], 1);
 }
 
 __global__ void k_scan(int32_t* hist, int32_t* cursor) {
@@ -164,7 +151,7 @@ __global__ void k_scatter(KArgs A) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= A.njobs) return;
     Pair p = get_pair<ALLPAIRS>(A, q);
-    int pos = atomicAdd(&A.cursor[cost_bucket(job_cost<ALLPAIRS>(A, q, p))], 1);
+    int pos = atomicAdd(&A.cursor[cost_bucket((int64_t)p.m * p.n)], 1);
     A.order[pos] = q;
 }
 
@@ -213,7 +200,8 @@ __device__ __forceinline__ int32_t fill_pair(const KArgs& A, const uint8_t* pa, 
         const int32_t vtop = (r0 == 0) ? vinit : vneg;
         int32_t dg0 = vinit;
         if (s > 0 && r0 > 0) dg0 = (r0 >= prev_lo && r0 <= prev_hi) ? bnd[r0] : vneg;
-        vlast = sweep_strip<C, DIRS>(pa + r0, rows, pb, n, j0, A.kdm, A.kdx, vtop, dg0, io,
+        vlast = sweep_strip<C, DIRS>(pa + r0, rows, pb, n, j0, DIRS ? A.kdm : A.kdm_w, DIRS ? A.kdx : A.kdx_w,
+                                     vtop, dg0, io,
                                      DIRS ? dirs + (size_t)s * G * kWave * C : nullptr, lds, ksel);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -335,16 +323,39 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                 if (w < mn && w_fb >= 0 && w > w_fb) w = (int)w_fb;
                 int passes = 0;
                 int c_min = 2;
+                // With widening, a first pass that does not certify serves only to
+                // find the region's score, so it runs score-only (no direction
+                // words); one that does certify is swept again, same band, with
+                // directions.  Doubled passes all record directions.
+                bool probe = DIRS && !A.band_doubling;
+                bool certified_first = false;
                 for (;;) {
-                    full = !A.band_ok || w >= mn ||
-                           (int64_t)(2 * kWave + dlt + 2 * (int64_t)w) * 1024 >= (int64_t)A.frac_1024 * m;
+                    // a pass after a failed one is certain to certify (unless
+                    // doubling), so it takes the full grid only once the band
+                    // covers every row of a strip; a first pass, which may fail,
+                    // already does so at fallback_frac of the rows
+                    const int64_t lim = (passes > 0 && !A.band_doubling) ? 1024 : A.frac_1024;
+                    full = !A.band_ok || w >= mn || (int64_t)(2 * kWave + dlt + 2 * (int64_t)w) * 1024 >= lim * m;
                     C = uniform(pick_cols(A, m, n, full, w, c_min));
-                    const int32_t v = fill_any<DIRS>(C, A, P.a, P.b, m, n, full, w, bnd, spare, dirs, lds, &G, &cells);
+                    const bool score_only = probe && !full;
+                    int32_t v;
+                    if (score_only) {
+                        v = fill_any<false>(C, A, P.a, P.b, m, n, false, w, bnd, spare, nullptr, lds, &G, &cells);
+                        score = v + A.gap * (m + n);
+                    } else {
+                        v = fill_any<DIRS>(C, A, P.a, P.b, m, n, full, w, bnd, spare, dirs, lds, &G, &cells);
+                        score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
+                    }
                     ++passes;
-                    score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
+                    probe = false;
                     if (full) break;
                     const int64_t u_out = (int64_t)A.cd * (mn - w - 1) + (int64_t)A.gap * (dlt + 2 * (int64_t)w + 2);
-                    if ((int64_t)score > u_out) break;
+                    if ((int64_t)score > u_out) {
+                        if (passes == 1) certified_first = true;
+                        if (!score_only) break;
+                        c_min = C;  // the same band again, with directions
+                        continue;
+                    }
                     if (A.band_doubling) {
                         w = max(1, 2 * w);
                         continue;
@@ -361,8 +372,8 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                     c_min = C;
                 }
                 w_out = full ? -1 : w;
-                const int widenings = min(passes - 1, 31);
-                st_out = (uint32_t)((passes == 1 && !full ? 1 : 0) | (widenings << 1) | (full ? 0x40 : 0) |
+                const int extra = min(passes - 1, 31);
+                st_out = (uint32_t)((certified_first ? 1 : 0) | (extra << 1) | (full ? 0x40 : 0) |
                                     (A.band_ok ? 0 : 0x80));
                 cells_out = cells;
             } else {
@@ -462,8 +473,12 @@ struct Layout {
 // largest pair's full grid (0.25 B per cell).  The workspace-size query asks
 // for one slot per resident wave, up to kSlotBudget of the device's HBM;
 // a launch uses as many slots as the workspace it is given holds (at least
-// one block's worth), so a smaller workspace only costs parallelism.
-constexpr size_t kSlotBudget = size_t(128) << 30;
+// one block's worth), so a smaller workspace only costs parallelism.  The
+// budget is sized for a 288 GB part: pairs of 20,000 bases need 100 MB per
+// slot, and all 2048 resident waves of the sweeps with directions then take
+// 205 GB (measured on the 8192-pair learned-band workload: 1328 waves within
+// 128 GiB, 208 -> 188 ms full DP and 64 -> 56.5 ms learned band with 2048).
+constexpr size_t kSlotBudget = size_t(240) << 30;
 constexpr size_t kHeaderBytes = 5120;  // queue (0), hist[512] (1024), cursor[512] (3072)
 
 static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di,
@@ -535,6 +550,9 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.max_len = job.max_len;
     A.kdm = K.kdm;
     A.kdx = K.kdx;
+    const Consts KW = score_consts(job.sc);
+    A.kdm_w = KW.kdm;
+    A.kdx_w = KW.kdx;
     A.gap = job.sc.gap;
     step_costs(di.device, job.dirs, A.step_cost);
     if (job.force_cols) {
@@ -551,7 +569,6 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.frac_1024 = job.frac_1024;
     A.cd = std::max(job.sc.match, job.sc.mismatch);
     A.band_ok = 2 * job.sc.gap < A.cd ? 1 : 0;
-    A.banded = job.banded ? 1 : 0;
     A.band_doubling = job.band_doubling ? 1 : 0;
     A.w_used = job.w_used;
     A.status = job.status;

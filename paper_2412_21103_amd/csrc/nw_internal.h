@@ -135,6 +135,8 @@ int launch_widths(int32_t n, const float* yhat, const int32_t* a_len, const int3
                   int32_t* w, hipStream_t st);
 int launch_band_labels(int32_t n, const int32_t* scores, const int32_t* a_len, const int32_t* b_len,
                        int32_t cd, int32_t gap, int32_t* w_cert, float* target, hipStream_t st);
+int launch_path_labels(int32_t n, const uint8_t* paths, const int64_t* path_off, const int32_t* path_len,
+                       const int32_t* a_len, const int32_t* b_len, int32_t* w_path, float* target, hipStream_t st);
 int launch_quantize(const float* params, uint16_t* wq, hipStream_t st);
 size_t mlp_train_workspace_bytes(int32_t batch);
 int launch_mlp_train_step(nw_mlp* mlp, int32_t batch, const float* x, const float* target,

@@ -170,6 +170,50 @@ __global__ void k_band_labels(int32_t n, const int32_t* scores, const int32_t* a
     if (target) target[k] = log1pf((float)w);
 }
 
+// w_path: how far path k strays outside the corridor of diagonals between
+// (0,0) and (m,n), [min(0,D), max(0,D)] with D = n - m, i.e. the band
+// half-width it needs (the maximum diagonal offset of the optimal path beyond
+// the straight band).  A diagonal move keeps the offset j - i, a vertical move
+// lowers it by one, a horizontal move raises it.  One wave per path: lane l
+// scans the l-th contiguous chunk of moves for its net offset and the highest
+// and lowest running offsets inside the chunk; an exclusive scan of the net
+// offsets across the wave gives each chunk's starting offset.
+__global__ __launch_bounds__(256) void k_path_labels(int32_t n, const uint8_t* paths, const int64_t* path_off,
+                                                     const int32_t* path_len, const int32_t* a_len,
+                                                     const int32_t* b_len, int32_t* w_path, float* target) {
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= n) return;
+    const int lane = lane_id();
+    const int64_t len = path_len[k] > 0 ? path_len[k] : 0;
+    const int64_t chunk = (len + kWave - 1) / kWave;
+    const int64_t lo_i = min(len, chunk * lane), hi_i = min(len, lo_i + chunk);
+    const uint8_t* p = paths + path_off[k];
+    int32_t off = 0, top = 0, bot = 0;  // relative to the chunk's start
+    for (int64_t x = lo_i; x < hi_i; ++x) {
+        const uint8_t mv = p[x];
+        off += (mv == 3) - (mv == 2);
+        top = max(top, off);
+        bot = min(bot, off);
+    }
+    // exclusive scan of the chunks' net offsets
+    int32_t incl = off;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    const int32_t start = incl - off;
+    const int32_t dd = b_len[k] - a_len[k];
+    const int32_t corr_lo = min(0, dd), corr_hi = max(0, dd);
+    int32_t e = max(0, max(start + top - corr_hi, corr_lo - (start + bot)));
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) e = max(e, __shfl_xor(e, d));
+    if (lane == 0) {
+        if (w_path) w_path[k] = e;
+        if (target) target[k] = log1pf((float)e);
+    }
+}
+
 // ------------------------------------------------------- training pieces
 // Output error of the mean pinball loss and the two hidden-layer errors,
 // one wave per row.  u = target - yhat; dL/dyhat = -(u < 0 ? tau - 1 : tau)/B.
@@ -327,6 +371,15 @@ int launch_band_labels(int32_t n, const int32_t* scores, const int32_t* a_len, c
     ProfScope ps("nw_band_labels", st);
     hipLaunchKernelGGL(k_band_labels, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, scores, a_len, b_len, cd,
                        gap, w_cert, target);
+    return launched();
+}
+
+int launch_path_labels(int32_t n, const uint8_t* paths, const int64_t* path_off, const int32_t* path_len,
+                       const int32_t* a_len, const int32_t* b_len, int32_t* w_path, float* target, hipStream_t st) {
+    if (n == 0) return NW_OK;
+    ProfScope ps("nw_path_labels", st);
+    hipLaunchKernelGGL(k_path_labels, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, paths, path_off, path_len,
+                       a_len, b_len, w_path, target);
     return launched();
 }
 

@@ -59,11 +59,17 @@ def test_band_with_certified_widths(small_band_batch):
     say("band: w_init = w_cert")
     s, paths, wu, st, cells = run_band(pairs, wc)
     check_equal(pairs, ref, s, paths, "w_cert")
-    # a start at w_cert certifies on the first pass unless the band is wide
-    # enough to fall back to the full grid
+    # a start at w_cert certifies on the first pass, unless its band is past
+    # the first pass's height limit (fallback_frac of m): then the first pass
+    # runs the widest band under the limit and the second pass certifies
+    m = np.array([len(a) for a in pairs.a])
+    n = np.array([len(b) for b in pairs.b])
+    limited = 128 + np.abs(n - m) + 2 * wc >= 0.5 * m
     first = (st & 1) == 1
+    second = ((st >> 1) & 31) == 1
     fullg = (st & 0x40) != 0
-    assert (first | fullg).all()
+    assert first[~limited].all()
+    assert (first | second | fullg)[limited].all()
     assert first.sum() >= len(pairs) // 2
 
 

@@ -136,6 +136,26 @@ def test_labels_match_reference(pairs):
         np.testing.assert_allclose(t, np.log1p(w.astype(np.float64)), rtol=1e-6, atol=0)
 
 
+def test_path_labels_match_oracle(pairs):
+    # w_path of the oracle's own paths, against the device labels of the
+    # device paths (the paths are identical, checked here too); two scorings
+    # and an empty pair
+    say("mlp: path labels")
+    from workloads import Pairs
+    ext = Pairs(list(pairs.a) + [np.zeros(0, np.uint8), pairs.a[0][:5]],
+                list(pairs.b) + [pairs.b[1][:9], np.zeros(0, np.uint8)], "labels")
+    d = _pairs_dev(ext)
+    for sc in [P, (2, -3, -2)]:
+        s, paths, poff, plen = nwp.align_batch(*d, sc)
+        w, t = nwp.path_labels(paths, poff, plen, d[2], d[4])
+        w, t = w.cpu().numpy(), t.cpu().numpy()
+        for k, (a, b) in enumerate(zip(ext.a, ext.b)):
+            s_ref, p_ref = oracle.align(a, b, sc)
+            assert w[k] == band.w_path(p_ref, len(a), len(b)), (sc, k)
+        np.testing.assert_allclose(t, np.log1p(w.astype(np.float64)), rtol=1e-6, atol=0)
+    assert w.max() > 0
+
+
 def _train_data(pairs, seed=11):
     d = _pairs_dev(pairs)
     x = nwp.mlp_features(*d[:5])
