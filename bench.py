@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs * SIMDs * lanes * clock: 39.32 T lane-ops/s
 FILL_OPS_PER_CELL = 5  # diagonal term, vertical add, max3, tag clear, tag shift
+SCORE_OPS_PER_CELL = 2  # score only: diagonal term, max3
 # counting optimal paths: diagonal term, max, three equality tests, six 32-bit selects, two 64-bit adds
 COUNT_OPS_PER_CELL = 13
 COOP_SOURCES = ["paper_2412_21103_amd/csrc/nw_common.h", "paper_2412_21103_amd/csrc/nw_strip.h",
@@ -165,6 +166,7 @@ def bench_band_batch(args):
             self.w_used = torch.empty(self.n, dtype=torch.int32, device=dev)
             self.status = torch.empty(self.n, dtype=torch.uint8, device=dev)
             self.swept = torch.empty(self.n, dtype=torch.int64, device=dev)
+            self.swept_so = torch.empty(self.n, dtype=torch.int64, device=dev)
 
     test, train = Batch(test_pairs), Batch(train_pairs)
     torch.cuda.synchronize()
@@ -201,7 +203,7 @@ def bench_band_batch(args):
     def const(B, w0, flags=0):
         st = L.nw_align_batch_banded(B.n, *[ptr(v) for v in B.d], B.max_len, sc, flags, vp(0), int(w0),
                                      ctypes.c_float(frac), ptr(B.scores), ptr(B.paths), ptr(B.poff), ptr(B.plen),
-                                     ptr(B.w_used), ptr(B.status), ptr(B.swept), ptr(ws), ws_bytes,
+                                     ptr(B.w_used), ptr(B.status), ptr(B.swept), ptr(B.swept_so), ptr(ws), ws_bytes,
                                      vp(stream.cuda_stream))
         if st != 0:
             raise nwp.NWError(st, "nw_align_batch_banded")
@@ -212,7 +214,7 @@ def bench_band_batch(args):
         st = L.nw_align_batch_learned(B.n, *[ptr(v) for v in B.d], B.max_len, sc, flags, ctypes.byref(net.state),
                                       ctypes.c_float(mg), ctypes.c_float(frac), ptr(B.scores), ptr(B.paths),
                                       ptr(B.poff), ptr(B.plen), ptr(B.w_used), ptr(B.status), ptr(B.swept),
-                                      ptr(ws), ws_bytes, vp(stream.cuda_stream))
+                                      ptr(B.swept_so), ptr(ws), ws_bytes, vp(stream.cuda_stream))
         if st != 0:
             raise nwp.NWError(st, "nw_align_batch_learned")
 
@@ -230,7 +232,7 @@ def bench_band_batch(args):
 
     def snapshot(B):
         return (B.scores.clone(), B.paths.clone(), B.plen.clone(), B.w_used.clone(), B.status.clone(),
-                B.swept.clone())
+                B.swept.clone(), B.swept_so.clone())
 
     # identical scores, lengths and every path byte (compared on the device)
     plen_idx = {}
@@ -294,12 +296,23 @@ def bench_band_batch(args):
     res_dbl_learned = arm("dbl_learned", wall_ld, ms_ld, prof_ld, out_ld, "nw_batch_banded")
 
     # roofline of the banded kernel in the learned arm: computed cells per launch
+    # roofline of the banded kernel in the learned arm: the cells of the passes
+    # with directions at FILL_OPS_PER_CELL, those of score-only passes at
+    # SCORE_OPS_PER_CELL (and again at the 7 and 5 operations per cell the
+    # scope counts name)
     kb = prof_l.get("nw_batch_banded")
     swept_cells = float(out_l[5].sum())
-    roof = alu_roofline("nw_batch_banded", swept_cells, kb[1] / kb[0] if kb else None, FILL_OPS_PER_CELL)
+    so_cells = float(out_l[6].sum())
+    dir_cells = swept_cells - so_cells
+    ops = FILL_OPS_PER_CELL * dir_cells + SCORE_OPS_PER_CELL * so_cells
+    roof = alu_roofline("nw_batch_banded", ops, kb[1] / kb[0] if kb else None, 1)
     if roof:
+        roof.pop("ops_per_cell")
+        roof.update({"cells_with_directions": dir_cells, "cells_score_only": so_cells,
+                     "ops_per_cell": {"with_directions": FILL_OPS_PER_CELL, "score_only": SCORE_OPS_PER_CELL}})
         roof["traffic"] = traffic_record(BAND_COUNTERS, BAND_SOURCES)
-        roof["frac_at_7_ops_per_cell"] = round(7 * swept_cells / (kb[1] / kb[0] * 1e-3) / 1e12 / PEAK_INT32_TOPS, 4)
+        ops_scope = 7 * dir_cells + 5 * so_cells
+        roof["frac_at_scope_counts"] = round(ops_scope / (kb[1] / kb[0] * 1e-3) / 1e12 / PEAK_INT32_TOPS, 4)
         roof["valu"] = valu_record(BAND_VALU, BAND_SOURCES)
 
     cpu = exact_oracle = None
@@ -366,6 +379,8 @@ def common_fields(args, value, ms_per_step, config, roofline, cpu, metric_suffix
 
 
 def alu_roofline(kernel, cells, kernel_ms, ops_per_cell):
+    """Algorithmic int32 lane-ops (cells x ops_per_cell) per second of the
+    kernel's own time, against the chip's int32 VALU peak."""
     if not kernel_ms:
         return None
     achieved = ops_per_cell * cells / (kernel_ms * 1e-3) / 1e12

@@ -16,9 +16,14 @@
  *
  * Conventions shared by every entry point:
  *  - Sequence a (length m) labels rows, sequence b (length n) labels columns.
- *  - Symbols are nucleotide codes 0..3 stored one per byte.  Only equality
- *    matters; the kernels read the two low bits of each byte, so values
- *    above 3 alias and are a caller error.
+ *  - Symbols are bytes, one per position, and any byte value is legal: only
+ *    equality matters (a match or a mismatch).  Nucleotide codes 0..3, or
+ *    any pair whose bytes take at most four values that one two-bit field
+ *    tells apart (the letters ACGT, ACGU, acgt...), run the fastest sweep;
+ *    other pairs (protein letters, N, arbitrary bytes) are swept by
+ *    comparing bytes, at about 7 instead of 5 operations per cell.  The band
+ *    model's k-mer features read the two low bits only, which affects its
+ *    widths (speed), never results.
  *  - Unless stated otherwise every pointer is a DEVICE pointer (memory from
  *    hipMalloc or a torch CUDA tensor on the current device), and every call
  *    is asynchronous on `stream` (a hipStream_t; NULL = the null stream).
@@ -237,7 +242,8 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  * grid); status[k] = bit 0 certified on the first pass, bits 1..5 number of
  * passes after the first, bit 6 full grid, bit 7 certificate not applicable;
  * cells[k] =
- * cells swept over all passes.  A pair with m == 0 or n == 0 reports
+ * cells swept over all passes; cells_score_only[k] = those of them swept
+ * score-only (the first pass's, when it ran without directions).  A pair with m == 0 or n == 0 reports
  * w_used -1, the full-grid bit and 0 cells; a pair over max_len reports
  * w_used -1, status 0 and 0 cells.
  * ------------------------------------------------------------------------ */
@@ -249,7 +255,8 @@ int nw_align_batch_banded(int32_t npairs, const uint8_t *pool, const int64_t *a_
                           int32_t max_len, nw_scoring sc, uint32_t flags, const int32_t *w_init,
                           int32_t w_default, float fallback_frac, int32_t *scores, uint8_t *paths,
                           const int64_t *path_off, int32_t *path_len, int32_t *w_used,
-                          uint8_t *status, int64_t *cells, void *ws, size_t ws_bytes, void *stream);
+                          uint8_t *status, int64_t *cells, int64_t *cells_score_only, void *ws,
+                          size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * All-pairs score matrix for the centre-star multiple alignment front end
@@ -454,8 +461,8 @@ int nw_align_batch_learned(int32_t npairs, const uint8_t *pool, const int64_t *a
                            int32_t max_len, nw_scoring sc, uint32_t flags, const nw_mlp *mlp,
                            float margin, float fallback_frac, int32_t *scores, uint8_t *paths,
                            const int64_t *path_off, int32_t *path_len, int32_t *w_used,
-                           uint8_t *status, int64_t *cells, void *ws, size_t ws_bytes,
-                           void *stream);
+                           uint8_t *status, int64_t *cells, int64_t *cells_score_only, void *ws,
+                           size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Autotuner for the batch engine (nw_align_batch, nw_align_batch_banded,

@@ -84,7 +84,7 @@ def lib():
         L.nw_align_batch_banded_workspace_size.argtypes = [_i32, _i32, _u32, ctypes.POINTER(_sz)]
         L.nw_align_batch_banded.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _u32, _vp,
                                             _i32, ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                            _vp, _sz, _vp]
+                                            _vp, _vp, _sz, _vp]
         _pm = ctypes.POINTER(MlpState)
         _f = ctypes.c_float
         L.nw_mlp_sync.argtypes = [_pm, _vp]
@@ -98,7 +98,7 @@ def lib():
         L.nw_mlp_train_epoch.argtypes = [_pm, _i32, _vp, _vp, _vp, _i32, _f, _f, _vp, _vp, _sz, _vp]
         L.nw_align_batch_learned_workspace_size.argtypes = [_i32, _i32, _u32, ctypes.POINTER(_sz)]
         L.nw_align_batch_learned.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, Scoring, _u32, _pm,
-                                             _f, _f, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+                                             _f, _f, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
         L.nw_autotune.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp, _vp]
         L.nw_allpairs_workspace_size.argtypes = [_i32, _i32, ctypes.POINTER(_sz)]
         L.nw_allpairs_scores.argtypes = [_i32, _vp, _vp, _vp, _i32, Scoring, _vp, _vp, _sz, _vp]
@@ -258,10 +258,11 @@ def align_batch_banded(pool: torch.Tensor, a_off: torch.Tensor, a_len: torch.Ten
                        scoring=PAPER_SCORING, w_init: torch.Tensor | None = None, w_default: int = 0,
                        fallback_frac: float = 0.5, score_only: bool = False,
                        path_off: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-                       stream=None, doubling: bool = False):
+                       stream=None, doubling: bool = False, cells_score_only: torch.Tensor | None = None):
     """Certified-band batch.  Returns ``(scores, paths, path_off, path_len, w_used, status,
     cells)`` (paths/path_off/path_len are None with ``score_only``).  ``doubling``
-    widens a failed band by doubling (NW_BAND_DOUBLING)."""
+    widens a failed band by doubling (NW_BAND_DOUBLING); ``cells_score_only``
+    (int64[npairs], optional) receives the cells swept score-only."""
     npairs = int(a_len.numel())
     flags = (SCORE_ONLY if score_only else 0) | (BAND_DOUBLING if doubling else 0)
     dev = _dev()
@@ -284,7 +285,7 @@ def align_batch_banded(pool: torch.Tensor, a_off: torch.Tensor, a_len: torch.Ten
                                      _ptr(b_len), int(max_len), _sc(scoring), flags, _ptr(w_init),
                                      int(w_default), float(fallback_frac), _ptr(scores), _ptr(paths),
                                      _ptr(path_off), _ptr(plen), _ptr(w_used), _ptr(status),
-                                     _ptr(cells), _ptr(ws), ws.numel(), _stream(stream))
+                                     _ptr(cells), _ptr(cells_score_only), _ptr(ws), ws.numel(), _stream(stream))
     _check(st, "nw_align_batch_banded")
     return scores, paths, path_off, plen, w_used, status, cells
 
@@ -418,7 +419,8 @@ def learned_workspace_size(npairs: int, max_len: int, flags: int = 0) -> int:
 
 def align_batch_learned(pool, a_off, a_len, b_off, b_len, max_len: int, mlp: Mlp, margin: float = 0.0,
                         scoring=PAPER_SCORING, fallback_frac: float = 0.5, score_only: bool = False,
-                        path_off=None, workspace=None, stream=None, doubling: bool = False):
+                        path_off=None, workspace=None, stream=None, doubling: bool = False,
+                        cells_score_only: torch.Tensor | None = None):
     """Learned-band batch; same returns and options as ``align_batch_banded``."""
     npairs = int(a_len.numel())
     flags = (SCORE_ONLY if score_only else 0) | (BAND_DOUBLING if doubling else 0)
@@ -435,7 +437,8 @@ def align_batch_learned(pool, a_off, a_len, b_off, b_len, max_len: int, mlp: Mlp
                                       _ptr(b_len), int(max_len), _sc(scoring), flags,
                                       ctypes.byref(mlp.state), float(margin), float(fallback_frac),
                                       _ptr(scores), _ptr(paths), _ptr(path_off), _ptr(plen),
-                                      _ptr(w_used), _ptr(status), _ptr(cells), _ptr(ws), ws.numel(),
+                                      _ptr(w_used), _ptr(status), _ptr(cells), _ptr(cells_score_only), _ptr(ws),
+                                      ws.numel(),
                                       _stream(stream))
     _check(st, "nw_align_batch_learned")
     return scores, paths, path_off, plen, w_used, status, cells

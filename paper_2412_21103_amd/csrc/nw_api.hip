@@ -588,7 +588,8 @@ static int run_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
                       const int64_t* b_off, const int32_t* b_len, int32_t max_len, nw_scoring sc,
                       uint32_t flags, const int32_t* w_init, int32_t w_default, float fallback_frac,
                       int32_t* scores, uint8_t* paths, const int64_t* path_off, int32_t* path_len,
-                      int32_t* w_used, uint8_t* status, int64_t* cells, void* ws, size_t ws_bytes,
+                      int32_t* w_used, uint8_t* status, int64_t* cells, int64_t* cells_so, void* ws,
+                      size_t ws_bytes,
                       hipStream_t stream, const DeviceInfo& di) {
     BatchJob J{};
     const bool dirs = !(flags & NW_SCORE_ONLY);
@@ -614,6 +615,7 @@ static int run_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_off,
     J.w_used = w_used;
     J.status = status;
     J.cells = cells;
+    J.cells_so = cells_so;
     return launch_batch(J, ws, ws_bytes, stream, di);
 }
 
@@ -641,7 +643,8 @@ int nw_align_batch_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_
                           int32_t max_len, nw_scoring sc, uint32_t flags, const int32_t* w_init,
                           int32_t w_default, float fallback_frac, int32_t* scores, uint8_t* paths,
                           const int64_t* path_off, int32_t* path_len, int32_t* w_used,
-                          uint8_t* status, int64_t* cells, void* ws, size_t ws_bytes, void* stream) {
+                          uint8_t* status, int64_t* cells, int64_t* cells_so, void* ws, size_t ws_bytes,
+                          void* stream) {
     if (w_default < 0) return NW_EINVAL;
     int st = check_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, fallback_frac,
                           scores, paths, path_off, path_len, ws, stream != nullptr);
@@ -653,11 +656,12 @@ int nw_align_batch_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_
                       graph_key({2, w((int64_t)npairs), w(pool), w(a_off), w(a_len), w(b_off), w(b_len),
                                  w((int64_t)max_len), wsc(sc), w((int64_t)flags), w(w_init), w((int64_t)w_default),
                                  w((int64_t)(fallback_frac * 1048576.f)), w(scores), w(paths), w(path_off),
-                                 w(path_len), w(w_used), w(status), w(cells), w(ws), w((int64_t)ws_bytes)}),
+                                 w(path_len), w(w_used), w(status), w(cells), w(cells_so), w(ws),
+                                 w((int64_t)ws_bytes)}),
                       s, [&] {
                           return run_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, w_init,
                                             w_default, fallback_frac, scores, paths, path_off, path_len, w_used,
-                                            status, cells, ws, ws_bytes, s, di);
+                                            status, cells, cells_so, ws, ws_bytes, s, di);
                       });
 }
 
@@ -799,8 +803,8 @@ int nw_align_batch_learned(int32_t npairs, const uint8_t* pool, const int64_t* a
                            const int64_t* b_off, const int32_t* b_len, int32_t max_len, nw_scoring sc,
                            uint32_t flags, const nw_mlp* mlp, float margin, float fallback_frac,
                            int32_t* scores, uint8_t* paths, const int64_t* path_off, int32_t* path_len,
-                           int32_t* w_used, uint8_t* status, int64_t* cells, void* ws, size_t ws_bytes,
-                           void* stream) {
+                           int32_t* w_used, uint8_t* status, int64_t* cells, int64_t* cells_so, void* ws,
+                           size_t ws_bytes, void* stream) {
     if (!mlp_ok(mlp, false) || !(margin >= 0.f) || margin > 1e6f) return NW_EINVAL;
     int st = check_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, fallback_frac, scores,
                           paths, path_off, path_len, ws, stream != nullptr);
@@ -820,14 +824,16 @@ int nw_align_batch_learned(int32_t npairs, const uint8_t* pool, const int64_t* a
         graph_key({3, w((int64_t)npairs), w(pool), w(a_off), w(a_len), w(b_off), w(b_len), w((int64_t)max_len),
                    wsc(sc), w((int64_t)flags), w(mlp->params), w(mlp->params_bf16),
                    w((int64_t)(margin * 1048576.f)), w((int64_t)(fallback_frac * 1048576.f)), w(scores), w(paths),
-                   w(path_off), w(path_len), w(w_used), w(status), w(cells), w(ws), w((int64_t)ws_bytes)}),
+                   w(path_off), w(path_len), w(w_used), w(status), w(cells), w(cells_so), w(ws),
+                   w((int64_t)ws_bytes)}),
         s, [&] {
             int r;
             if ((r = launch_features(npairs, pool, a_off, a_len, b_off, b_len, x, s))) return r;
             if ((r = launch_mlp_forward(npairs, x, mlp->params, mlp->params_bf16, yhat, s, di))) return r;
             if ((r = launch_widths(npairs, yhat, a_len, b_len, margin, wv, s))) return r;
             return run_banded(npairs, pool, a_off, a_len, b_off, b_len, max_len, sc, flags, wv, 0, fallback_frac,
-                              scores, paths, path_off, path_len, w_used, status, cells, ws, band_bytes, s, di);
+                              scores, paths, path_off, path_len, w_used, status, cells, cells_so, ws, band_bytes,
+                              s, di);
         });
 }
 

@@ -22,7 +22,7 @@ constexpr int kBlockThreads = kWave * kWavesPerBlock;
 // latencies (all-pairs 83 -> 67 ms); sweeps with directions keep 2: more would
 // stretch each pair's wave, and the largest pairs already set the makespan.
 constexpr int blocks_per_cu(bool dirs) { return dirs ? 2 : 4; }
-constexpr int kBuckets = 512;
+constexpr int kBuckets = 512;  // cost buckets per alphabet class
 
 struct KArgs {
     int32_t njobs, nseq;
@@ -36,6 +36,7 @@ struct KArgs {
     int32_t* w_used;
     uint8_t* status;
     int64_t* cells;
+    int64_t* cells_so;      // of those, the cells of score-only passes
     const uint8_t* pool;
     const int64_t* a_off;
     const int32_t* a_len;
@@ -55,10 +56,13 @@ struct KArgs {
     int64_t* path_len64;
     int32_t* matrix;
     // workspace
-    int32_t* queue;
+    int32_t* queue;   // next position of the four-symbol part of the order
+    int32_t* queue2;  // next position of the wide part
+    int32_t* n_narrow;  // positions 0 .. n_narrow-1 hold pairs of at most four distinct bytes
     int32_t* hist;
     int32_t* cursor;
     int32_t* order;
+    uint32_t* masks;  // byte-presence masks, eight words per sequence (pairs: a of job k at 2k, b at 2k+1)
     int32_t* bnd;
     int64_t bnd_stride;
     uint32_t* dirs;
@@ -114,6 +118,20 @@ __device__ __forceinline__ Pair get_pair(const KArgs& A, int job) {
 
 // ---- planning kernels: zero the counters, bucket jobs by cost, scatter ----
 
+// Byte-presence mask of every sequence (seq_mask), one wave per sequence.
+// Sequence q is a pair's a (q even) or b (q odd), or, for all-pairs, the q-th
+// sequence.
+template <bool ALLPAIRS>
+__global__ __launch_bounds__(256) void k_alpha(KArgs A, int32_t nseq) {
+    __shared__ uint32_t bits[4][8];
+    const int wave = threadIdx.x >> 6;
+    const int q = blockIdx.x * 4 + wave;
+    if (q >= nseq) return;
+    const int64_t off = ALLPAIRS ? A.a_off[q] : ((q & 1) ? A.b_off[q >> 1] : A.a_off[q >> 1]);
+    const int32_t len = ALLPAIRS ? A.a_len[q] : ((q & 1) ? A.b_len[q >> 1] : A.a_len[q >> 1]);
+    seq_mask(A.pool + off, max(len, 0), A.masks + (int64_t)q * 8, bits[wave]);
+}
+
 __global__ void k_zero(int32_t* p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -128,30 +146,71 @@ __device__ __forceinline__ int cost_bucket(int64_t cost) {
     return 8 * e + (int)((cost >> (e - 3)) & 7);
 }
 
+// Mask indices of job q's two sequences.
+template <bool ALLPAIRS>
+__device__ __forceinline__ void mask_index(const Pair& p, int q, int64_t* qa, int64_t* qb) {
+    *qa = ALLPAIRS ? p.row : 2 * (int64_t)q;
+    *qb = ALLPAIRS ? p.col : 2 * (int64_t)q + 1;
+}
+
+// Bucket of job q: its cost bucket, plus kBuckets if the pair needs the
+// byte-comparing sweep (code_shift < 0).
+template <bool ALLPAIRS>
+__device__ __forceinline__ int job_bucket(const KArgs& A, int q) {
+    Pair p = get_pair<ALLPAIRS>(A, q);
+    bool wide = false;
+    if (p.m > 0 && p.n > 0) {
+        int64_t qa, qb;
+        mask_index<ALLPAIRS>(p, q, &qa, &qb);
+        wide = code_shift(A.masks + qa * 8, A.masks + qb * 8) < 0;
+    }
+    return cost_bucket((int64_t)p.m * p.n) + (wide ? kBuckets : 0);
+}
+
 template <bool ALLPAIRS>
 __global__ void k_hist(KArgs A) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= A.njobs) return;
-    Pair p = get_pair<ALLPAIRS>(A, q);
-    atomicAdd(&A.hist[cost_bucket((int64_t)p.m * p.n)], 1);
+    atomicAdd(&A.hist[job_bucket<ALLPAIRS>(A, q)], 1);
 }
 
-__global__ void k_scan(int32_t* hist, int32_t* cursor) {
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int b = kBuckets - 1; b >= 0; --b) {
-            cursor[b] = run;
-            run += hist[b];
-        }
+// Start of every bucket in the order: the four-symbol pairs first, largest
+// cost first, then the wide pairs, largest first; n_narrow is where the wide
+// part begins.  One wave: lane l takes ranks 16l .. 16l+15 (rank r < 512 is
+// four-symbol bucket 511 - r, rank r >= 512 wide bucket 1535 - r).
+__global__ __launch_bounds__(64) void k_scan(int32_t* hist, int32_t* cursor, int32_t* n_narrow) {
+    constexpr int kPer = 2 * kBuckets / kWave;
+    const int lane = lane_id();
+    auto bucket = [](int r) { return r < kBuckets ? kBuckets - 1 - r : 3 * kBuckets - 1 - r; };
+    int32_t h[kPer];
+    int32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        h[k] = hist[bucket(kPer * lane + k)];
+        sum += h[k];
     }
+    int32_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    int32_t run = incl - sum;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        cursor[bucket(kPer * lane + k)] = run;
+        run += h[k];
+    }
+    // the four-symbol part ends after lane 31 (rank 511)
+    const int32_t narrow = __shfl(incl, kWave / 2 - 1);
+    if (lane == 0) *n_narrow = narrow;
 }
 
 template <bool ALLPAIRS>
 __global__ void k_scatter(KArgs A) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= A.njobs) return;
-    Pair p = get_pair<ALLPAIRS>(A, q);
-    int pos = atomicAdd(&A.cursor[cost_bucket((int64_t)p.m * p.n)], 1);
+    int pos = atomicAdd(&A.cursor[job_bucket<ALLPAIRS>(A, q)], 1);
     A.order[pos] = q;
 }
 
@@ -171,9 +230,9 @@ constexpr int32_t kNegW = -(1 << 29);      // -infinity in the W domain
 // outside the region are -infinity; the first row and column keep their
 // values.  Returns V (or W) at (m, n); *G_out gets the direction groups per
 // strip and *cells the number of cells swept.
-template <int C, bool DIRS>
+template <int C, bool DIRS, bool WIDE>
 __device__ __forceinline__ int32_t fill_pair(const KArgs& A, const uint8_t* pa, const uint8_t* pb,
-                                             int m, int n, bool full, int w, int32_t* bnd,
+                                             int m, int n, uint32_t shift, bool full, int w, int32_t* bnd,
                                              int32_t* spare, uint32_t* dirs, uint32_t* lds, int* G_out,
                                              int64_t* cells) {
     constexpr int kCols = kWave * C;
@@ -200,8 +259,8 @@ __device__ __forceinline__ int32_t fill_pair(const KArgs& A, const uint8_t* pa, 
         const int32_t vtop = (r0 == 0) ? vinit : vneg;
         int32_t dg0 = vinit;
         if (s > 0 && r0 > 0) dg0 = (r0 >= prev_lo && r0 <= prev_hi) ? bnd[r0] : vneg;
-        vlast = sweep_strip<C, DIRS>(pa + r0, rows, pb, n, j0, DIRS ? A.kdm : A.kdm_w, DIRS ? A.kdx : A.kdx_w,
-                                     vtop, dg0, io,
+        vlast = sweep_strip<C, DIRS, WIDE>(pa + r0, rows, pb, n, j0, DIRS ? A.kdm : A.kdm_w, DIRS ? A.kdx : A.kdx_w,
+                                           shift, vtop, dg0, io,
                                      DIRS ? dirs + (size_t)s * G * kWave * C : nullptr, lds, ksel);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -241,13 +300,15 @@ __device__ __forceinline__ int pick_cols(const KArgs& A, int m, int n, bool full
     return best;
 }
 
-template <bool DIRS>
+// One pass with sweep width C; WIDE: the byte-comparing sweep (pairs with
+// more than four distinct bytes).
+template <bool DIRS, bool WIDE>
 __device__ __forceinline__ int32_t fill_any(int C, const KArgs& A, const uint8_t* pa, const uint8_t* pb, int m,
-                                            int n, bool full, int w, int32_t* bnd, int32_t* spare, uint32_t* dirs,
-                                            uint32_t* lds, int* G, int64_t* cells) {
-    if (C == 8) return fill_pair<8, DIRS>(A, pa, pb, m, n, full, w, bnd, spare, dirs, lds, G, cells);
-    if (C == 4) return fill_pair<4, DIRS>(A, pa, pb, m, n, full, w, bnd, spare, dirs, lds, G, cells);
-    return fill_pair<2, DIRS>(A, pa, pb, m, n, full, w, bnd, spare, dirs, lds, G, cells);
+                                            int n, uint32_t shift, bool full, int w, int32_t* bnd, int32_t* spare,
+                                            uint32_t* dirs, uint32_t* lds, int* G, int64_t* cells) {
+    if (C == 8) return fill_pair<8, DIRS, WIDE>(A, pa, pb, m, n, shift, full, w, bnd, spare, dirs, lds, G, cells);
+    if (C == 4) return fill_pair<4, DIRS, WIDE>(A, pa, pb, m, n, shift, full, w, bnd, spare, dirs, lds, G, cells);
+    return fill_pair<2, DIRS, WIDE>(A, pa, pb, m, n, shift, full, w, bnd, spare, dirs, lds, G, cells);
 }
 
 __device__ __forceinline__ int64_t walk_any(int C, const uint32_t* dirs, int m, int n, int G, uint32_t* lds,
@@ -257,7 +318,10 @@ __device__ __forceinline__ int64_t walk_any(int C, const uint32_t* dirs, int m, 
     return walk_back<2>(dirs, m, n, G, lds, rev, band_hi);
 }
 
-template <bool DIRS, bool ALLPAIRS, bool BANDED>
+// WIDE: this launch serves the wide part of the order (pairs with more than
+// four distinct bytes) with the byte-comparing sweep; otherwise the
+// four-symbol part with the one-hot lookup.
+template <bool DIRS, bool ALLPAIRS, bool BANDED, bool WIDE>
 __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KArgs A) {
     __shared__ uint32_t smem[kWavesPerBlock][StripShape<8>::kLdsWords];
     const int wave = threadIdx.x >> 6;
@@ -274,21 +338,30 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
     // 0, so lane 0 reads the ticket), and every lane stores the same outputs.
     // A lane-0-only branch near the back edge lets the compiler split the loop
     // per lane, after which readfirstlane no longer reads lane 0.
+    const int part_lo = WIDE ? uniform(*A.n_narrow) : 0;
+    const int part_hi = WIDE ? A.njobs : uniform(*A.n_narrow);
     for (;;) {
-        const int p = uniform(atomicAdd(A.queue, lane == 0 ? 1 : 0));
-        if (p >= A.njobs) break;
+        const int p = part_lo + uniform(atomicAdd(WIDE ? A.queue2 : A.queue, lane == 0 ? 1 : 0));
+        if (p >= part_hi) break;
         const int job = uniform(A.order[p]);
         const Pair P = get_pair<ALLPAIRS>(A, job);
         const int m = uniform(P.m), n = uniform(P.n);
 
         int32_t score;
         bool ok = (m <= A.max_len && n <= A.max_len && m >= 0 && n >= 0);
+        // the pair's code field (the wide part of the order compares bytes)
+        uint32_t shift = 0;
+        if (!WIDE && ok && m > 0 && n > 0) {
+            int64_t qa, qb;
+            mask_index<ALLPAIRS>(P, job, &qa, &qb);
+            shift = (uint32_t)max(0, uniform(code_shift(A.masks + qa * 8, A.masks + qb * 8)));
+        }
         int64_t plen = 0;
         // banded outputs for pairs that never reach the band loop: no band,
         // no cells (an empty pair counts as solved on the full grid)
         int32_t w_out = -1;
         uint32_t st_out = ok ? (0x40u | (A.band_ok ? 0u : 0x80u)) : 0u;
-        int64_t cells_out = 0;
+        int64_t cells_out = 0, cells_so_out = 0;
         if (!ok) {
             score = INT32_MIN;
             plen = -1;
@@ -340,10 +413,14 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                     const bool score_only = probe && !full;
                     int32_t v;
                     if (score_only) {
-                        v = fill_any<false>(C, A, P.a, P.b, m, n, false, w, bnd, spare, nullptr, lds, &G, &cells);
+                        const int64_t before = cells;
+                        v = fill_any<false, WIDE>(C, A, P.a, P.b, m, n, shift, false, w, bnd, spare, nullptr, lds, &G,
+                                                  &cells);
+                        cells_so_out += cells - before;
                         score = v + A.gap * (m + n);
                     } else {
-                        v = fill_any<DIRS>(C, A, P.a, P.b, m, n, full, w, bnd, spare, dirs, lds, &G, &cells);
+                        v = fill_any<DIRS, WIDE>(C, A, P.a, P.b, m, n, shift, full, w, bnd, spare, dirs, lds, &G,
+                                                 &cells);
                         score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
                     }
                     ++passes;
@@ -378,7 +455,8 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                 cells_out = cells;
             } else {
                 C = uniform(pick_cols(A, m, n, true, 0));
-                const int32_t v = fill_any<DIRS>(C, A, P.a, P.b, m, n, true, 0, bnd, spare, dirs, lds, &G, &cells);
+                const int32_t v =
+                    fill_any<DIRS, WIDE>(C, A, P.a, P.b, m, n, shift, true, 0, bnd, spare, dirs, lds, &G, &cells);
                 score = (DIRS ? ((v - 1) >> 2) : v) + A.gap * (m + n);
             }
             if constexpr (DIRS && !ALLPAIRS) {
@@ -406,6 +484,7 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                 if (A.w_used) A.w_used[job] = w_out;
                 if (A.status) A.status[job] = (uint8_t)st_out;
                 if (A.cells) A.cells[job] = cells_out;
+                if (A.cells_so) A.cells_so[job] = cells_so_out;
             }
         }
     }
@@ -465,7 +544,7 @@ constexpr int kMaxCols = 8;  // slots are sized for the widest sweep, which boun
 
 struct Layout {
     int64_t nslots, grid;
-    size_t off_order, off_bnd, off_dirs, off_rev, total;
+    size_t off_order, off_masks, off_bnd, off_dirs, off_rev, total;
     int64_t bnd_stride, dirs_stride, rev_stride;
 };
 
@@ -479,7 +558,8 @@ struct Layout {
 // 205 GB (measured on the 8192-pair learned-band workload: 1328 waves within
 // 128 GiB, 208 -> 188 ms full DP and 64 -> 56.5 ms learned band with 2048).
 constexpr size_t kSlotBudget = size_t(240) << 30;
-constexpr size_t kHeaderBytes = 5120;  // queue (0), hist[512] (1024), cursor[512] (3072)
+// queue (0), queue2 (4), n_narrow (8), hist[1024] (1024), cursor[1024] (5120)
+constexpr size_t kHeaderBytes = 9216;
 
 static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const DeviceInfo& di,
                          size_t ws_limit = SIZE_MAX) {
@@ -494,7 +574,10 @@ static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const Device
     // bytes per block of slots (the three per-slot arrays are padded per array)
     const size_t per_block = (size_t)kWavesPerBlock * ((size_t)L.bnd_stride * 4 + (size_t)L.dirs_stride * 4 +
                                                        (size_t)L.rev_stride);
-    const size_t fixed = align_up(kHeaderBytes + (size_t)std::max(njobs, 1) * 4, 256) + 3 * 256;
+    // masks: eight words for each of the 2 njobs sequences (pairs), which also
+    // covers the nseq <= njobs sequences of all-pairs
+    const size_t mask_bytes = align_up((size_t)std::max(njobs, 1) * 2 * 32, 256);
+    const size_t fixed = align_up(kHeaderBytes + (size_t)std::max(njobs, 1) * 4, 256) + mask_bytes + 3 * 256;
     const int64_t want = ((int64_t)njobs + kWavesPerBlock - 1) / kWavesPerBlock;
     int64_t grid = std::min<int64_t>(std::max<int64_t>(want, 1), (int64_t)di.cus * blocks_per_cu(dirs));
     const size_t budget = std::min(ws_limit, fixed + std::max(kSlotBudget, per_block));
@@ -509,6 +592,8 @@ static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const Device
     size_t off = kHeaderBytes;
     L.off_order = off;
     off = align_up(off + (size_t)std::max(njobs, 1) * 4, 256);
+    L.off_masks = off;
+    off += mask_bytes;
     L.off_bnd = off;
     off = align_up(off + (size_t)L.nslots * L.bnd_stride * 4, 256);
     L.off_dirs = off;
@@ -525,12 +610,20 @@ size_t batch_workspace_bytes(int32_t njobs, int32_t max_len, bool dirs, const De
     return layout_for(njobs, max_len, dirs, di).total;
 }
 
+// The four-symbol part, then the wide part (a launch that finds the wide
+// part empty exits at once).
 template <bool DIRS, bool ALLPAIRS, bool BANDED>
 static void launch_engine(const KArgs& A, int64_t grid, hipStream_t st) {
-    ProfScope ps(BANDED ? (DIRS ? "nw_batch_banded" : "nw_batch_banded_score")
-                        : (ALLPAIRS ? "nw_allpairs" : (DIRS ? "nw_batch" : "nw_batch_score")),
-                 st);
-    hipLaunchKernelGGL((k_batch<DIRS, ALLPAIRS, BANDED>), dim3((unsigned)grid), dim3(kBlockThreads), 0, st, A);
+    {
+        ProfScope ps(BANDED ? (DIRS ? "nw_batch_banded" : "nw_batch_banded_score")
+                            : (ALLPAIRS ? "nw_allpairs" : (DIRS ? "nw_batch" : "nw_batch_score")),
+                     st);
+        hipLaunchKernelGGL((k_batch<DIRS, ALLPAIRS, BANDED, false>), dim3((unsigned)grid), dim3(kBlockThreads), 0,
+                           st, A);
+    }
+    ProfScope ps("nw_batch_wide", st);
+    hipLaunchKernelGGL((k_batch<DIRS, ALLPAIRS, BANDED, true>), dim3((unsigned)grid), dim3(kBlockThreads), 0, st,
+                       A);
 }
 
 int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st, const DeviceInfo& di) {
@@ -573,10 +666,14 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.w_used = job.w_used;
     A.status = job.status;
     A.cells = job.cells;
+    A.cells_so = job.cells_so;
     A.queue = (int32_t*)base;
+    A.queue2 = (int32_t*)(base + 4);
+    A.n_narrow = (int32_t*)(base + 8);
     A.hist = (int32_t*)(base + 1024);
-    A.cursor = (int32_t*)(base + 3072);
+    A.cursor = (int32_t*)(base + 5120);
     A.order = (int32_t*)(base + L.off_order);
+    A.masks = (uint32_t*)(base + L.off_masks);
     A.bnd = (int32_t*)(base + L.off_bnd);
     A.bnd_stride = L.bnd_stride;
     A.dirs = (uint32_t*)(base + L.off_dirs);
@@ -588,14 +685,17 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     const unsigned pb = (unsigned)((job.njobs + 255) / 256);
     constexpr int kHeaderInts = (int)(kHeaderBytes / 4);
     hipLaunchKernelGGL(k_zero, dim3((kHeaderInts + 255) / 256), dim3(256), 0, st, (int32_t*)base, kHeaderInts);
+    const int32_t nseq = job.allpairs ? job.nseq : 2 * job.njobs;
+    if (job.allpairs) hipLaunchKernelGGL(k_alpha<true>, dim3((nseq + 3) / 4), dim3(256), 0, st, A, nseq);
+    else hipLaunchKernelGGL(k_alpha<false>, dim3((nseq + 3) / 4), dim3(256), 0, st, A, nseq);
     if (job.allpairs) {
         hipLaunchKernelGGL(k_hist<true>, dim3(pb), dim3(256), 0, st, A);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor, A.n_narrow);
         hipLaunchKernelGGL(k_scatter<true>, dim3(pb), dim3(256), 0, st, A);
         launch_engine<false, true, false>(A, L.grid, st);
     } else {
         hipLaunchKernelGGL(k_hist<false>, dim3(pb), dim3(256), 0, st, A);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor, A.n_narrow);
         hipLaunchKernelGGL(k_scatter<false>, dim3(pb), dim3(256), 0, st, A);
         if (job.banded) {
             if (job.dirs) launch_engine<true, false, true>(A, L.grid, st);

@@ -81,6 +81,87 @@ __device__ __forceinline__ uint32_t row_word(uint32_t x, int32_t kdm, int32_t kd
     return base ^ ((uint32_t)((kdm ^ kdx) & 0xFF) << (8u * (x & 3u)));
 }
 
+// Symbol codes.  Only equality of bytes matters (a match or a mismatch), and
+// the substitution lookup above handles four codes.  A pair whose bytes take
+// at most four distinct values that one two-bit field, bits k and k+1, tells
+// apart is swept with code (x >> k) & 3: k = 0 for nucleotide codes 0..3,
+// k = 1 for the letters ACGT, ACGU or acgt.  Other pairs compare bytes.
+__device__ __forceinline__ uint32_t sym_code(uint32_t x, uint32_t shift) { return (x >> shift) & 3u; }
+
+// The field offset k for a pair from its two byte-presence masks (eight words
+// each, bit x set when byte x occurs), or -1 if the pair needs the
+// byte-comparing sweep (more than four distinct bytes, or no separating field).
+__device__ __forceinline__ int code_shift(const uint32_t* ma, const uint32_t* mb) {
+    uint32_t sy = 0;  // up to four distinct bytes, one per byte of sy
+    int count = 0;
+    for (int i = 0; i < 8; ++i) {
+        uint32_t u = ma[i] | mb[i];
+        while (u != 0) {
+            if (count == 4) return -1;
+            sy |= (32u * (uint32_t)i + (uint32_t)__builtin_ctz(u)) << (8 * count);
+            ++count;
+            u &= u - 1;
+        }
+    }
+    for (int k = 0; k < 7; ++k) {
+        uint32_t seen = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < count) seen |= 1u << (((sy >> (8 * c)) >> k) & 3u);
+        if (__popc(seen) == count) return k;
+    }
+    return -1;
+}
+
+// Pairs with more than four distinct bytes compare bytes instead.  The row
+// word holds the row's byte in bits 0..8 (0x100 outside 1..m, which equals no
+// byte) and, above them, the term a mismatch adds: kdx, or -128 outside 1..m
+// (which freezes the lane as above).  A cell's diagonal candidate is then
+// diag + (byte == b_j ? kdm : that term).
+__device__ __forceinline__ uint32_t wide_word(bool valid, uint32_t x, int32_t kdx) {
+    return valid ? ((x & 0xFFu) | ((uint32_t)kdx << 9)) : (0x100u | ((uint32_t)(int32_t)kSentinelKd << 9));
+}
+
+// Byte-presence mask (eight words, bit x for byte x) of bytes p[0..len), by
+// one wave; the result is in lane l's `mask` for l < 8.  One pass ORs the
+// bytes (16 at a time where the address allows); if they are all nucleotide
+// codes 0..3 the mask lists all four (a superset, which still gives the field
+// offset 0), otherwise a second pass sets each byte's bit in `bits` (eight LDS
+// words of this wave).
+__device__ __forceinline__ uint32_t chunk_mask(const uint8_t* p, int64_t len, uint32_t* bits) {
+    const int lane = lane_id();
+    uint32_t acc = 0;
+    const int64_t head = min(len, (int64_t)((16u - ((uint32_t)(uintptr_t)p & 15u)) & 15u));
+    if (lane < head) acc |= p[lane];
+    const uint4* q = reinterpret_cast<const uint4*>(p + head);
+    const int64_t nvec = (len - head) >> 4;
+    for (int64_t v = lane; v < nvec; v += kWave) {
+        const uint4 x = q[v];
+        acc |= x.x | x.y | x.z | x.w;
+    }
+    const int64_t tail0 = head + (nvec << 4);
+    if (tail0 + lane < len) acc |= p[tail0 + lane];
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) acc |= (uint32_t)__shfl_xor((int32_t)acc, d);
+    if ((acc & 0xFCFCFCFCu) == 0) return lane == 0 ? 0xFu : 0u;
+    if (lane < 8) bits[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int64_t x = lane; x < len; x += kWave) {
+        const uint32_t c = p[x];
+        atomicOr(&bits[c >> 5], 1u << (c & 31u));
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    return lane < 8 ? bits[lane] : 0u;
+}
+
+// The mask of a whole sequence by one wave, stored to out[0..8).
+__device__ __forceinline__ void seq_mask(const uint8_t* p, int64_t len, uint32_t* out, uint32_t* bits) {
+    const uint32_t m = chunk_mask(p, len, bits);
+    if (lane_id() < 8) out[lane_id()] = m;
+}
+
 // Coherent (L1-bypassing) load of data written earlier by this or another
 // wave on the same device.
 __device__ __forceinline__ int32_t load_coherent(const int32_t* p) {

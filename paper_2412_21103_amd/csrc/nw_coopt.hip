@@ -90,12 +90,30 @@ struct CoArgs {
     int64_t off_walk;  // within a slot
     int32_t spin;      // polls before a team wait gives up
     uint32_t* fault;   // host-visible device-fault word (may be null)
+    uint32_t* masks;   // byte-presence masks: a of pair p at 16p, b at 16p+8
 };
 
 __device__ __forceinline__ int cost_bucket(int64_t cost) {
     if (cost < 8) return (int)max<int64_t>(cost, 0);
     const int e = 63 - __builtin_clzll((unsigned long long)cost);
     return 8 * e + (int)((cost >> (e - 3)) & 7);
+}
+
+// Byte-presence masks of every pair's two sequences (seq_mask), one wave each.
+__global__ __launch_bounds__(256) void k_co_alpha(CoArgs A) {
+    __shared__ uint32_t bits[4][8];
+    const int wave = threadIdx.x >> 6;
+    const int q = blockIdx.x * 4 + wave;
+    if (q >= 2 * A.npairs) return;
+    const int p = q >> 1;
+    const int64_t off = (q & 1) ? A.b_off[p] : A.a_off[p];
+    const int32_t len = (q & 1) ? A.b_len[p] : A.a_len[p];
+    seq_mask(A.pool + off, max(len, 0), A.masks + (int64_t)q * 8, bits[wave]);
+}
+
+// The pair's code field (code_shift), or -1 to compare bytes.
+__device__ __forceinline__ int pair_shift(const CoArgs& A, int p) {
+    return uniform(code_shift(A.masks + (int64_t)p * 16, A.masks + (int64_t)p * 16 + 8));
 }
 
 __device__ __forceinline__ bool pair_ok(const CoArgs& A, int p) {
@@ -255,17 +273,20 @@ __device__ __forceinline__ void publish_rows(int64_t* prog, int s, int32_t rows)
 // `bin` (s > 0) and writes its own last column to `bout` (if not the last
 // strip).  The lane that holds column n leaves its row-m values in w_end and
 // n_end (last strip only).
-template <bool ENUM>
+// WIDE compares bytes (wide_word row words); otherwise bytes are codes
+// (x >> shift) & 3 looked up through the one-hot dot product.
+template <bool ENUM, bool WIDE>
 __device__ void fill_strip(const CoArgs& A, WaveLds& S, const uint8_t* a, const uint8_t* b, int32_t m, int32_t n,
-                           int s, int nstrips, const BCell* bin, BCell* bout, const Hand& H, uint32_t* tie,
-                           int32_t& w_end, Count& n_end) {
+                           uint32_t shift, int s, int nstrips, const BCell* bin, BCell* bout, const Hand& H,
+                           uint32_t* tie, int32_t& w_end, Count& n_end) {
     const int lane = lane_id();
     const int32_t steps = m + kWave - 1;
     const int64_t groups = ((int64_t)steps + 3) / 4;
     const int j0 = s * kCoStrip;
     const int32_t c0 = j0 + 2 * lane + 1, c1 = c0 + 1;
-    const uint32_t oh0 = 1u << (8 * (c0 <= n ? (b[c0 - 1] & 3) : 0));
-    const uint32_t oh1 = 1u << (8 * (c1 <= n ? (b[c1 - 1] & 3) : 0));
+    const uint32_t x0 = c0 <= n ? (uint32_t)b[c0 - 1] : 0u, x1 = c1 <= n ? (uint32_t)b[c1 - 1] : 0u;
+    const uint32_t oh0 = WIDE ? x0 : 1u << (8 * sym_code(x0, shift));
+    const uint32_t oh1 = WIDE ? x1 : 1u << (8 * sym_code(x1, shift));
     // lanes past column n stay at row 0; rows run 1..m for the others
     const uint32_t rows = c0 <= n ? (uint32_t)m : 0u;
     const bool hand = lane == kWave - 1 && s + 1 < nstrips;
@@ -281,7 +302,8 @@ __device__ void fill_strip(const CoArgs& A, WaveLds& S, const uint8_t* a, const 
             const int32_t r = T + 1 + lane;
             if (s > 0 && H.prog_in) wait_rows(H.prog_in, ((int64_t)s << 32) | (uint32_t)min(T + kWave, m), H.err, H.spin);
             const uint32_t older = T == 0 ? 0u : S.rw[kWave + lane];
-            const uint32_t word = r <= m ? row_word(a[r - 1] & 3u, A.kdm, A.kdx) : 0u;
+            const uint32_t word = r > m ? 0u : WIDE ? wide_word(true, a[r - 1], A.kdx)
+                                                    : row_word(sym_code(a[r - 1], shift), A.kdm, A.kdx);
             BCell c{0, 1u, 0u, 0u};
             if (s > 0 && r <= m) c = load_bcell(bin + r);
             __builtin_amdgcn_wave_barrier();
@@ -315,9 +337,14 @@ __device__ void fill_strip(const CoArgs& A, WaveLds& S, const uint8_t* a, const 
             if (!CHECK || rm1 < rows) {
                 int32_t nw0, nw1;
                 Count nn0, nn1;
-                const int32_t cd0 = __builtin_amdgcn_sdot4(rw, (int32_t)oh0, dw, false);
+                // bytes compared: the row's byte against the column's (oh0/oh1)
+                const uint32_t rbyte = (uint32_t)rw & 0x1FFu;
+                const int32_t rmis = rw >> 9;
+                const int32_t cd0 = WIDE ? dw + (rbyte == oh0 ? A.kdm : rmis)
+                                         : __builtin_amdgcn_sdot4(rw, (int32_t)oh0, dw, false);
                 const uint32_t b0 = cell(cd0, w0, lw, dn, n0, ln, nw0, nn0);
-                const int32_t cd1 = __builtin_amdgcn_sdot4(rw, (int32_t)oh1, w0, false);
+                const int32_t cd1 = WIDE ? w0 + (rbyte == oh1 ? A.kdm : rmis)
+                                         : __builtin_amdgcn_sdot4(rw, (int32_t)oh1, w0, false);
                 const uint32_t b1 = cell(cd1, w1, nw0, n0, n1, nn0, nw1, nn1);
                 w0 = nw0;
                 n0 = nn0;
@@ -371,8 +398,8 @@ __device__ void fill_strip(const CoArgs& A, WaveLds& S, const uint8_t* a, const 
 
 // The fill of one pair (m, n >= 1) by one wave: strips in order, the
 // boundary column alternating between the two buffers of the wave's slot.
-template <bool ENUM>
-__device__ void fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int32_t m, int32_t n,
+template <bool ENUM, bool WIDE>
+__device__ void fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int32_t m, int32_t n, uint32_t shift,
                           int32_t& w_end, Count& n_end) {
     const uint8_t* a = A.pool + A.a_off[p];
     const uint8_t* b = A.pool + A.b_off[p];
@@ -382,8 +409,8 @@ __device__ void fill_pair(const CoArgs& A, uint8_t* slot, WaveLds& S, int p, int
     const int nstrips = (n + kCoStrip - 1) / kCoStrip;
     const Hand solo{nullptr, nullptr, nullptr, 0};
     for (int s = 0; s < nstrips; ++s)
-        fill_strip<ENUM>(A, S, a, b, m, n, s, nstrips, bnd + (s & 1) * bstride, bnd + ((s & 1) ^ 1) * bstride, solo,
-                         tie, w_end, n_end);
+        fill_strip<ENUM, WIDE>(A, S, a, b, m, n, shift, s, nstrips, bnd + (s & 1) * bstride,
+                               bnd + ((s & 1) ^ 1) * bstride, solo, tie, w_end, n_end);
 }
 
 // Scalar walk state: moves, remaining options and the cell before each move.
@@ -467,13 +494,20 @@ __global__ __launch_bounds__(kWave * kCoWaves, co_blocks_per_cu(ENUM)) void k_co
             const int nstrips = (n + kCoStrip - 1) / kCoStrip;
             const uint8_t* a = A.pool + A.a_off[p];
             const uint8_t* b = A.pool + A.b_off[p];
+            const int sh = (m > 0 && n > 0) ? pair_shift(A, p) : 0;
             int32_t w_end = 0;
             Count n_end{1u, 0u, 0u};
             for (int s = wv; s < nstrips; s += kCoWaves) {
                 const Hand H{s > 0 ? &prog[(s - 1) % kTeamRing] : nullptr,
                              s + 1 < nstrips ? &prog[s % kTeamRing] : nullptr, &team_err, A.spin};
-                fill_strip<false>(A, lds[wv], a, b, m, n, s, nstrips, s > 0 ? ring((s - 1) % kTeamRing) : nullptr,
-                                  ring(s % kTeamRing), H, nullptr, w_end, n_end);
+                if (sh < 0)
+                    fill_strip<false, true>(A, lds[wv], a, b, m, n, 0u, s, nstrips,
+                                            s > 0 ? ring((s - 1) % kTeamRing) : nullptr, ring(s % kTeamRing), H,
+                                            nullptr, w_end, n_end);
+                else
+                    fill_strip<false, false>(A, lds[wv], a, b, m, n, (uint32_t)sh, s, nstrips,
+                                             s > 0 ? ring((s - 1) % kTeamRing) : nullptr, ring(s % kTeamRing), H,
+                                             nullptr, w_end, n_end);
             }
             __syncthreads();
             if (wv == (nstrips - 1) % kCoWaves) {
@@ -505,7 +539,9 @@ __global__ __launch_bounds__(kWave * kCoWaves, co_blocks_per_cu(ENUM)) void k_co
             int32_t w_end = 0;
             Count n_end{1u, 0u, 0u};
             if (m > 0 && n > 0) {
-                fill_pair<ENUM>(A, slot, lds[wv], p, m, n, w_end, n_end);
+                const int sh = pair_shift(A, p);
+                if (sh < 0) fill_pair<ENUM, true>(A, slot, lds[wv], p, m, n, 0u, w_end, n_end);
+                else fill_pair<ENUM, false>(A, slot, lds[wv], p, m, n, (uint32_t)sh, w_end, n_end);
                 // the lane that holds column n at row m has the result
                 const int src = ((n - 1) % kCoStrip) / kCoCols;
                 w_end = __shfl(w_end, src);
@@ -563,7 +599,7 @@ __global__ __launch_bounds__(kWave * kCoWaves, co_blocks_per_cu(ENUM)) void k_co
 
 struct CoLayout {
     int64_t slot_bytes, off_tie, off_walk;
-    size_t off_order, off_slots;
+    size_t off_order, off_masks, off_slots;
     int64_t full_slots;
 };
 
@@ -584,7 +620,8 @@ CoLayout co_layout(int32_t npairs, int32_t max_len, int32_t k, const DeviceInfo&
     }
     L.slot_bytes = off;
     L.off_order = kCoHeader;
-    L.off_slots = align_up(kCoHeader + (size_t)std::max(npairs, 1) * 4, 256);
+    L.off_masks = align_up(kCoHeader + (size_t)std::max(npairs, 1) * 4, 256);
+    L.off_slots = align_up(L.off_masks + (size_t)std::max(npairs, 1) * 64, 256);
     const int64_t resident = (int64_t)di.cus * co_blocks_per_cu(k > 0) * kCoWaves;
     const int64_t needed = ((int64_t)std::max(npairs, 1) + kCoWaves - 1) / kCoWaves * kCoWaves;
     L.full_slots = std::min(resident, needed);
@@ -636,6 +673,7 @@ int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, 
     // pairs of 2^16 cells or more are filled by teams (counts only)
     A.team_bucket = k > 0 ? kCoBuckets : NW_COOPT_TEAM_BUCKET;
     A.order = (int32_t*)(base + L.off_order);
+    A.masks = (uint32_t*)(base + L.off_masks);
     A.slots = base + L.off_slots;
     A.slot_bytes = L.slot_bytes;
     A.off_tie = L.off_tie;
@@ -644,6 +682,7 @@ int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, 
     A.fault = di.fault;
     const unsigned pg = (unsigned)((npairs + 255) / 256);
     hipLaunchKernelGGL(k_co_zero, dim3((kCoHeaderInts + 255) / 256), dim3(256), 0, st, A.hist, kCoHeaderInts);
+    hipLaunchKernelGGL(k_co_alpha, dim3((unsigned)((2 * (int64_t)npairs + 3) / 4)), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_co_hist, dim3(pg), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_co_scan, dim3(1), dim3(kCoBuckets), 0, st, A);
     hipLaunchKernelGGL(k_co_scatter, dim3(pg), dim3(256), 0, st, A);

@@ -87,6 +87,7 @@ struct BatchJob {
     int32_t* w_used;
     uint8_t* status;
     int64_t* cells;
+    int64_t* cells_so;  // of those, swept score-only
     // 0: sweep width per pass from the cost table; 2, 4 or 8: that width
     // always (used by the autotuner)
     int force_cols;

@@ -55,6 +55,7 @@ struct CoopArgs {
     int32_t spin;           // polls before a boundary wait gives up
     int32_t* score;
     uint32_t* fault;        // host-visible device-fault word (may be null)
+    const uint32_t* masks;  // byte-presence masks of a and b (eight words each), written by k_coop_alpha
 };
 
 // Dynamic LDS of a block: the waves' row tables, then one boundary ring per
@@ -71,8 +72,8 @@ struct CoopLds {
 };
 
 template <int C, bool DIRS, int IN, int OUT>
-__device__ __forceinline__ int32_t coop_sweep(const CoopArgs& A, uint32_t epoch, int s, int wave, uint32_t* lds,
-                                              uint32_t* dyn, int j0, int ksel) {
+__device__ __forceinline__ int32_t coop_sweep(const CoopArgs& A, uint32_t epoch, uint32_t shift, bool wide, int s,
+                                              int wave, uint32_t* lds, uint32_t* dyn, int j0, int ksel) {
     lds_u64* rings = (lds_u64*)(dyn + CoopLds<C>::kTableWordsAligned);
     lds_i32* consumed = (lds_i32*)(dyn + CoopLds<C>::kCountWord);
     uint64_t* col = A.bnd + (int64_t)s * A.bnd_stride;
@@ -89,8 +90,12 @@ __device__ __forceinline__ int32_t coop_sweep(const CoopArgs& A, uint32_t epoch,
                                    epoch,
                                    A.err,
                                    A.spin};
-    return sweep_strip<C, DIRS>(A.a, A.m, A.b, A.n, j0, A.kdm, A.kdx, A.vinit, A.vinit, io,
-                                DIRS ? A.dirs + (size_t)s * A.G * kWave * C : nullptr, lds, ksel);
+    uint32_t* dirs = DIRS ? A.dirs + (size_t)s * A.G * kWave * C : nullptr;
+    if (wide)
+        return sweep_strip<C, DIRS, true>(A.a, A.m, A.b, A.n, j0, A.kdm, A.kdx, shift, A.vinit, A.vinit, io, dirs, lds,
+                                          ksel);
+    return sweep_strip<C, DIRS, false>(A.a, A.m, A.b, A.n, j0, A.kdm, A.kdx, shift, A.vinit, A.vinit, io, dirs, lds,
+                                       ksel);
 }
 
 template <int C, bool DIRS>
@@ -104,6 +109,10 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
     // a captured graph never accept a previous replay's slots)
     const uint32_t epoch = (uint32_t)uniform((int32_t)__hip_atomic_load(A.epoch, __ATOMIC_RELAXED,
                                                                           __HIP_MEMORY_SCOPE_AGENT));
+    // the pair's code field, or compared bytes
+    const int shift_or = uniform(code_shift(A.masks, A.masks + 8));
+    const bool wide = shift_or < 0;
+    const uint32_t shift = (uint32_t)max(shift_or, 0);
     for (;;) {
         if (threadIdx.x == 0) ticket_s = atomicAdd(A.ticket, 1);
         __syncthreads();
@@ -123,17 +132,17 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
             // input: none (first strip), the block's previous wave (LDS), or the
             // previous block's last wave (HBM); output likewise
             if (s == 0) {
-                v = last ? coop_sweep<C, DIRS, kIoNone, kIoNone>(A, epoch, s, wave, lds, dyn, j0, ksel)
-                         : coop_sweep<C, DIRS, kIoNone, kIoLds>(A, epoch, s, wave, lds, dyn, j0, ksel);
+                v = last ? coop_sweep<C, DIRS, kIoNone, kIoNone>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoNone, kIoLds>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel);
             } else if (wave == 0) {
-                v = last ? coop_sweep<C, DIRS, kIoGlobal, kIoNone>(A, epoch, s, wave, lds, dyn, j0, ksel)
-                         : coop_sweep<C, DIRS, kIoGlobal, kIoLds>(A, epoch, s, wave, lds, dyn, j0, ksel);
+                v = last ? coop_sweep<C, DIRS, kIoGlobal, kIoNone>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoGlobal, kIoLds>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel);
             } else if (wave < kCoopWaves - 1) {
-                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, epoch, s, wave, lds, dyn, j0, ksel)
-                         : coop_sweep<C, DIRS, kIoLds, kIoLds>(A, epoch, s, wave, lds, dyn, j0, ksel);
+                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoLds, kIoLds>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel);
             } else {
-                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, epoch, s, wave, lds, dyn, j0, ksel)
-                         : coop_sweep<C, DIRS, kIoLds, kIoGlobal>(A, epoch, s, wave, lds, dyn, j0, ksel);
+                v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel)
+                         : coop_sweep<C, DIRS, kIoLds, kIoGlobal>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel);
             }
             if (last) {
                 const int lsel = (A.n - 1 - j0) / C;
@@ -497,8 +506,28 @@ __global__ __launch_bounds__(kCoopThreads) void k_tb_emit(TbArgs T) {
     }
 }
 
-// Workspace header words of the cooperative engine.
-constexpr int kHdrTicket = 0, kHdrErr = 16, kHdrSummary = 32, kHdrEpoch = 48;
+// Workspace header words of the cooperative engine (the masks take words
+// 64..79).
+constexpr int kHdrTicket = 0, kHdrErr = 16, kHdrSummary = 32, kHdrEpoch = 48, kHdrMasks = 64;
+constexpr size_t kCoopHeaderBytes = 512;
+
+// Byte-presence masks of a and b (zeroed by k_prep): every wave takes a
+// chunk of kAlphaChunk bytes of a, or of b, and ORs its chunk_mask in.
+constexpr int64_t kAlphaChunk = 8192;
+__global__ __launch_bounds__(256) void k_coop_alpha(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n,
+                                                    uint32_t* masks) {
+    __shared__ uint32_t bits[4][8];
+    const int wave = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t ca = (m + kAlphaChunk - 1) / kAlphaChunk;
+    const bool on_a = w < ca;
+    const int64_t start = (on_a ? w : w - ca) * kAlphaChunk;
+    const int64_t len = on_a ? m : n;
+    if (start >= len) return;
+    const uint32_t mk = chunk_mask((on_a ? a : b) + start, min(kAlphaChunk, len - start), bits[wave]);
+    const int lane = lane_id();
+    if (lane < 8 && mk != 0) atomicOr(masks + (on_a ? 0 : 8) + lane, mk);
+}
 
 // The slot tag of the latest cooperative fill on this device.  A boundary
 // slot is taken as ready once it carries the reading call's tag, so no two
@@ -511,11 +540,11 @@ constexpr int kHdrTicket = 0, kHdrErr = 16, kHdrSummary = 32, kHdrEpoch = 48;
 // moves them on.
 __device__ uint32_t g_coop_tag;
 
-// Before each fill: clear the ticket, the failure flag and the traceback
-// summary, and take the call's slot tag.
+// Before each fill: clear the ticket, the failure flag, the traceback summary
+// and the byte masks, and take the call's slot tag.
 __global__ void k_prep(int32_t* hdr, uint32_t host_epoch) {
     const int i = threadIdx.x;
-    if (i < kHdrEpoch) hdr[i] = 0;
+    if (i < kHdrEpoch || (i >= kHdrMasks && i < kHdrMasks + 16)) hdr[i] = 0;
     if (i == 0) {
         uint32_t prev = __hip_atomic_load(&g_coop_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t tag;
@@ -553,7 +582,7 @@ static CoopLayout coop_layout(int64_t m, int64_t n, bool dirs) {
     L.seg_stride = (int64_t)align_up((size_t)(m + cols + 16), 64);
     L.info_stride = kInfoHead + 3 * cols;
     const size_t ns = (size_t)L.nstrips;
-    size_t off = 256;
+    size_t off = kCoopHeaderBytes;
     L.off_bnd = off;
     off = align_up(off + (size_t)L.nstrips * L.bnd_stride * 8, 256);  // one column per strip
     L.off_dirs = off;
@@ -625,7 +654,13 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
     A.spin = di.spin_limit;
     A.score = score;
     A.fault = di.fault;
-    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, st, hdr, next_epoch());
+    A.masks = (const uint32_t*)(hdr + kHdrMasks);
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(128), 0, st, hdr, next_epoch());
+    {
+        const int64_t chunks = (m + kAlphaChunk - 1) / kAlphaChunk + (n + kAlphaChunk - 1) / kAlphaChunk;
+        hipLaunchKernelGGL(k_coop_alpha, dim3((unsigned)std::max<int64_t>(1, (chunks + 3) / 4)), dim3(256), 0, st, a,
+                           m, b, n, (uint32_t*)(hdr + kHdrMasks));
+    }
     const int grid = std::max(1, std::min(L.ngroups, di.cus));
     hipError_t e = dirs ? launch_coop_kernel<true>(A, grid, st) : launch_coop_kernel<false>(A, grid, st);
     if (e != hipSuccess) return NW_EDEVICE;

@@ -248,9 +248,14 @@ __device__ __forceinline__ typename IO::Slot wait_slot(const IO& io, int r, bool
     return x;
 }
 
-// Row word of grid row r of the sweep (r in 1..m), from its base code x.
-__device__ __forceinline__ uint32_t table_word(int r, int m, uint32_t x, int kdm, int kdx) {
-    return (r >= 1 && r <= m) ? row_word(x, kdm, kdx) : kSentinelWord;
+// Row word of grid row r of the sweep (r in 1..m), from its byte x: the
+// substitution terms of x's code (sym_code with the pair's field offset), or,
+// when bytes are compared, the byte and its mismatch term (wide_word).
+template <bool WIDE>
+__device__ __forceinline__ uint32_t table_word(int r, int m, uint32_t x, int kdm, int kdx, uint32_t shift) {
+    const bool valid = (r >= 1 && r <= m);
+    if constexpr (WIDE) return wide_word(valid, x, kdx);
+    else return valid ? row_word(sym_code(x, shift), kdm, kdx) : kSentinelWord;
 }
 
 // Write row r's word to the table (index r & 255, and its mirror copy when the
@@ -262,16 +267,17 @@ __device__ __forceinline__ void table_put(uint32_t* tab, int r, uint32_t w, bool
 }
 
 // Sweep one strip.  Returns, per lane, V (or W) of its column `ksel` after
-// the last row (the frozen final value).
+// the last row (the frozen final value).  Bytes are compared through their
+// codes (sym_code with the pair's field offset `shift`), or directly (WIDE).
 // `a` points at the sweep's first row and `m` counts its rows (a band sweeps
 // grid rows r0+1 .. r0+m with a = seq + r0).  Every lane starts from `vtop`,
 // the row above the sweep (the grid's first row, or -infinity inside a band),
 // except that lane 0's first diagonal input is `dg0`, the previous strip's
 // last column one row above the sweep.
-template <int C, bool DIRS, class IO>
+template <int C, bool DIRS, bool WIDE, class IO>
 __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, int m,
                                                const uint8_t* __restrict__ b, int n, int j0, int kdm,
-                                               int kdx, int32_t vtop, int32_t dg0, const IO& io,
+                                               int kdx, uint32_t shift, int32_t vtop, int32_t dg0, const IO& io,
                                                uint32_t* __restrict__ dirs, uint32_t* lds, int ksel) {
     const int lane = lane_id();
     const bool lane0 = (lane == 0);
@@ -284,18 +290,19 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
         acc0[k] = 0;
         acc1[k] = 0;
         int j = j0 + C * lane + k;
-        bcode[k] = (j < n) ? (uint32_t)(b[j] & 3) : 0u;
+        const uint32_t x = (j < n) ? (uint32_t)b[j] : 0u;
+        bcode[k] = WIDE ? x : sym_code(x, shift);
     }
-    uint32_t onehot[C];  // 1 in byte b[j] of column j: selects that row-word byte in v_dot4
+    uint32_t onehot[C];  // 1 in byte (code of b[j]) of column j: selects that row-word byte in v_dot4
 #pragma unroll
-    for (int k = 0; k < C; ++k) onehot[k] = 1u << (8 * bcode[k]);
+    for (int k = 0; k < C; ++k) onehot[k] = 1u << (8 * (bcode[k] & 3u));
     int32_t Dg = lane0 ? dg0 : vtop;
 
     // Row table: rows -63 .. 64 serve groups 0 and 1; each group end writes the
     // rows of the group after next, from base codes loaded two groups earlier.
     for (int p = lane; p < 128; p += kWave) {
         const int r = p - 63;
-        table_put(lds, r, table_word(r, m, (r >= 1 && r <= m) ? a[r - 1] : 0u, kdm, kdx), false);
+        table_put(lds, r, table_word<WIDE>(r, m, (r >= 1 && r <= m) ? a[r - 1] : 0u, kdm, kdx, shift), false);
     }
     const int mc = max(m, 1);
     uint32_t pfa = a[min(max(65 + lane, 1), mc) - 1];  // rows 65..96: written at the end of group 0
@@ -343,10 +350,15 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
             uint32_t rw;
             if constexpr (kHoist) rw = rwh[u];
             else rw = lds[base + u];
+            // wide alphabets: the row's byte and its mismatch term
+            const uint32_t rbyte = rw & 0x1FFu;
+            const int32_t rmis = (int32_t)rw >> 9;
 #pragma unroll
             for (int k = 0; k < C; ++k) {
                 const int32_t up = V[k];
-                const int32_t cD = __builtin_amdgcn_sdot4((int)rw, (int)onehot[k], diag, false);
+                int32_t cD;
+                if constexpr (WIDE) cD = diag + ((rbyte == bcode[k]) ? kdm : rmis);
+                else cD = __builtin_amdgcn_sdot4((int)rw, (int)onehot[k], diag, false);
                 int32_t v;
                 if constexpr (DIRS) {
                     const int32_t cU = up + 1;
@@ -398,7 +410,7 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
         if constexpr (IO::kPrefetch == 0) Rin = io.load(rin, lane < kGroup);
         {
             const int r = kGroup * g + 2 * kGroup + 1 + lane;  // table rows of group g + 2
-            table_put(lds, r, table_word(r, m, pf, kdm, kdx), lane >= kGroup);
+            table_put(lds, r, table_word<WIDE>(r, m, pf, kdm, kdx, shift), lane >= kGroup);
             pf = a[min(max(r + 2 * kGroup, 1), mc) - 1];  // rows of group g + 4, written at the end of g + 2
         }
         if constexpr (DIRS) {

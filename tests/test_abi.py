@@ -107,4 +107,4 @@ def test_band_model_host_checks():
     assert L.nw_mlp_features(-2, vp(1), vp(1), vp(1), vp(1), vp(1), vp(1), vp(0)) == nwp.NW_EINVAL
     assert L.nw_align_batch_learned(4, vp(1), vp(1), vp(1), vp(1), vp(1), 10, P, 0, ctypes.byref(st),
                                     f(0.1), f(0.5), vp(1), vp(1), vp(1), vp(1), vp(0), vp(0), vp(0),
-                                    vp(1), 1 << 30, vp(0)) == nwp.NW_EINVAL
+                                    vp(0), vp(1), 1 << 30, vp(0)) == nwp.NW_EINVAL

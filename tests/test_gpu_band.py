@@ -24,14 +24,14 @@ def _dev(x, dt):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to("cuda")
 
 
-def run_band(pairs, w_init, scoring=P, w_default=0, frac=0.5, doubling=False):
+def run_band(pairs, w_init, scoring=P, w_default=0, frac=0.5, doubling=False, so=None):
     pool, ao, al, bo, bl = pack_pairs(pairs)
     ml = int(max(al.max(), bl.max()))
     wi = None if w_init is None else _dev(w_init, np.int32)
     s, paths, poff, plen, wu, st, cells = nwp.align_batch_banded(
         _dev(pool, np.uint8), _dev(ao, np.int64), _dev(al, np.int32), _dev(bo, np.int64),
         _dev(bl, np.int32), ml, scoring, w_init=wi, w_default=w_default, fallback_frac=frac,
-        doubling=doubling)
+        doubling=doubling, cells_score_only=so)
     torch.cuda.synchronize()
     paths = paths.cpu().numpy()
     poff = poff.cpu().numpy()
@@ -76,8 +76,10 @@ def test_band_with_certified_widths(small_band_batch):
 def test_band_doubling_from_zero(small_band_batch):
     pairs, ref = small_band_batch
     say("band: w_init = 0 (doubling)")
-    s, paths, wu, st, cells = run_band(pairs, None, w_default=0, doubling=True)
+    so = torch.full((len(pairs),), -1, dtype=torch.int64, device="cuda")
+    s, paths, wu, st, cells = run_band(pairs, None, w_default=0, doubling=True, so=so)
     check_equal(pairs, ref, s, paths, "w0=0")
+    assert (so.cpu().numpy() == 0).all()  # doubling records directions on every pass
     doublings = (st >> 1) & 31
     assert doublings.max() >= 2
     # the certified width is never below the closed-form minimum
@@ -93,10 +95,16 @@ def test_band_widening_to_certified_width(small_band_batch, w0):
     # more than two passes, and the final width is at least w_cert.
     pairs, ref = small_band_batch
     say(f"band: w_init = {w0}, widening to the certified width")
-    s, paths, wu, st, cells = run_band(pairs, None, w_default=w0)
+    so = torch.full((len(pairs),), -1, dtype=torch.int64, device="cuda")
+    s, paths, wu, st, cells = run_band(pairs, None, w_default=w0, so=so)
     check_equal(pairs, ref, s, paths, f"w0={w0}")
-    widenings = (st >> 1) & 31
+    # the first pass runs score-only unless it is the full grid: its cells are
+    # counted there, and every later pass records directions
+    so = so.cpu().numpy()
     fullg = (st & 0x40) != 0
+    assert (so >= 0).all() and (so < cells).all()
+    assert (so[~fullg] > 0).all()
+    widenings = (st >> 1) & 31
     assert (widenings <= 1).all()
     if w0 == 0:
         assert (widenings[~fullg] == 1).sum() > 0

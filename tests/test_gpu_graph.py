@@ -68,7 +68,7 @@ def _banded(B, out, extra, ws, flags, stream):
     p = lambda t: vp(t.data_ptr())
     return nwp.lib().nw_align_batch_banded(B.n, *B.ins(), B.max_len, nwp.Scoring(1, -1, -1), flags, None, 4,
                                            ctypes.c_float(0.5), p(s), p(paths), p(B.poff), p(plen),
-                                           p(w_used), p(status), p(cells), p(ws), ws.numel(),
+                                           p(w_used), p(status), p(cells), vp(0), p(ws), ws.numel(),
                                            vp(stream.cuda_stream))
 
 
