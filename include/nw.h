@@ -485,6 +485,16 @@ int nw_autotune(int32_t npairs, const uint8_t *pool, const int64_t *a_off, const
                 uint8_t *paths, const int64_t *path_off, int32_t *path_len, void *ws,
                 size_t ws_bytes, int32_t *costs, void *stream);
 
+/* The current device's sweep-width cost table (host int32[6]: widths
+ * 128/256/512 with directions, then score-only) and whether it was set by
+ * nw_autotune or nw_set_sweep_costs (*tuned, may be NULL). */
+int nw_sweep_costs(int32_t *costs, int32_t *tuned);
+
+/* Install a cost table on the current device (host int32[6], each 1..2^20),
+ * e.g. one measured by nw_autotune in an earlier process and kept by the
+ * caller.  Only speed depends on it: every width gives identical results. */
+int nw_set_sweep_costs(const int32_t *costs);
+
 /* Release host-side caches: the NW_GRAPH graphs and the autotuned cost
  * tables.  Call only when no library work is in flight on any stream. */
 void nw_release_caches(void);

@@ -21,7 +21,8 @@ __all__ = [
     "profile_end", "align_batch_banded", "banded_workspace_size", "Mlp", "MLP_INPUTS",
     "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_widths", "band_labels", "path_labels", "mlp_train_step",
     "mlp_train_epoch", "align_batch_learned", "learned_workspace_size", "autotune", "init", "sync",
-    "set_wait_limit", "align_noalloc", "align_noalloc_fits",
+    "set_wait_limit", "align_noalloc", "align_noalloc_fits", "sweep_costs", "set_sweep_costs",
+    "autotune_cached",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -114,6 +115,8 @@ def lib():
         L.nw_set_wait_limit.argtypes = [_i32]
         L.nw_set_wait_limit.restype = ctypes.c_int
         L.nw_release_caches.restype = None
+        L.nw_sweep_costs.argtypes = [_vp, _vp]
+        L.nw_set_sweep_costs.argtypes = [_vp]
         L.nw_profile_begin.restype = ctypes.c_int
         L.nw_profile_end.argtypes = [ctypes.POINTER(KernelTime), _i32, ctypes.POINTER(_i32)]
         _lib = L
@@ -457,6 +460,46 @@ def autotune(pool, a_off, a_len, b_off, b_len, max_len: int, stream=None):
                              int(max_len), _ptr(scores), _ptr(paths), _ptr(path_off), _ptr(plen), _ptr(ws),
                              ws.numel(), costs, _stream(stream)), "nw_autotune")
     return {"dirs": list(costs[:3]), "score": list(costs[3:])}
+
+
+def sweep_costs():
+    """The current device's sweep-width cost table and whether it is tuned:
+    ({"dirs": [c128, c256, c512], "score": [...]}, tuned)."""
+    costs = (ctypes.c_int32 * 6)()
+    tuned = ctypes.c_int32(0)
+    _check(lib().nw_sweep_costs(costs, ctypes.byref(tuned)), "nw_sweep_costs")
+    return {"dirs": list(costs[:3]), "score": list(costs[3:])}, bool(tuned.value)
+
+
+def set_sweep_costs(table):
+    """Install {"dirs": [...], "score": [...]} as the current device's table."""
+    costs = (ctypes.c_int32 * 6)(*[int(x) for x in list(table["dirs"]) + list(table["score"])])
+    _check(lib().nw_set_sweep_costs(costs), "nw_set_sweep_costs")
+
+
+def autotune_cached(path, pool, a_off, a_len, b_off, b_len, max_len: int, config_class: str = "batch",
+                    stream=None):
+    """The autotuned cost table, kept in a JSON file under a key of (GPU
+    architecture, compute-unit count, config class): installed from the file
+    when the key is there, else measured with ``autotune`` on the given sample
+    and added to the file.  Returns (table, measured)."""
+    import json
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    key = f"{props.gcnArchName.split(':')[0]}|cu{props.multi_processor_count}|{config_class}"
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+    if key in cache:
+        set_sweep_costs(cache[key])
+        return cache[key], False
+    table = autotune(pool, a_off, a_len, b_off, b_len, max_len, stream)
+    cache[key] = table
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return table, True
 
 
 def center_star_workspace_size(nseq: int, max_len: int) -> int:

@@ -285,6 +285,28 @@ int nw_set_wait_limit(int32_t polls) {
     return NW_OK;
 }
 
+int nw_sweep_costs(int32_t* costs, int32_t* tuned) {
+    if (!costs) return NW_EINVAL;
+    DeviceInfo di;
+    const int st = device_info(&di);
+    if (st) return st;
+    step_costs(di.device, true, costs);
+    step_costs(di.device, false, costs + 3);
+    if (tuned) *tuned = tuned_costs(di.device) ? 1 : 0;
+    return NW_OK;
+}
+
+int nw_set_sweep_costs(const int32_t* costs) {
+    if (!costs) return NW_EINVAL;
+    for (int c = 0; c < 6; ++c)
+        if (costs[c] < 1 || costs[c] > (1 << 20)) return NW_EINVAL;
+    DeviceInfo di;
+    const int st = device_info(&di);
+    if (st) return st;
+    set_step_costs(di.device, costs, costs + 3);
+    return NW_OK;
+}
+
 void nw_release_caches(void) {
     release_graphs();
     reset_step_costs();

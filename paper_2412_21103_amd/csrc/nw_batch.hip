@@ -512,7 +512,13 @@ Tuning& tuning() {
 }
 }  // namespace
 
-static void step_costs(int device, bool dirs, int32_t out[3]) {
+bool tuned_costs(int device) {
+    Tuning& T = tuning();
+    std::lock_guard<std::mutex> lock(T.mu);
+    return device >= 0 && device < kMaxDevices && T.tuned[device];
+}
+
+void step_costs(int device, bool dirs, int32_t out[3]) {
     Tuning& T = tuning();
     std::lock_guard<std::mutex> lock(T.mu);
     const bool have = device >= 0 && device < kMaxDevices && T.tuned[device];

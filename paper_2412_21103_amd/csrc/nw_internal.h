@@ -125,6 +125,8 @@ int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, 
 
 // Sweep-width cost table (per device), filled by nw_autotune.
 void set_step_costs(int device, const int32_t dirs[3], const int32_t score[3]);
+void step_costs(int device, bool dirs, int32_t out[3]);
+bool tuned_costs(int device);
 void reset_step_costs();
 
 // Band model (nw_mlp.hip).
