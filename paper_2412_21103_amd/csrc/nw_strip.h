@@ -499,8 +499,10 @@ struct DirWindow {
 
 // Walk the stored directions of one pair from (m, n) back to (0, 0), one wave.
 // The walk is one dependent chain of lookups, so it runs on wave-uniform
-// scalar state and each move costs a few scalar operations and one
-// v_readlane:
+// scalar state.  Optimal paths are mostly diagonal, so the 64 lanes read the
+// tags of the next 64 diagonal cells at once and the walk takes a whole run of
+// diagonal moves in one step; every other move costs a few scalar operations
+// and one v_readlane:
 //  - the cell's strip s, lane l, column k and step t = i - r0(s) - 1 + l are
 //    kept up to date move by move, without divisions (tags 2 and 3 step up a
 //    row, tags 1 and 3 step left a column);
@@ -554,7 +556,48 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
         const int xo = ((3 - gw) << (4 + kLogC)) + ((15 - lw) << kLogC);
         int cur_r = -1;
         uint32_t cur = 0;
+        bool diag = true;
         for (;;) {
+            if (diag) {
+                // Diagonal run (tried at a new window and after a diagonal
+                // move, so runs of gap moves pay nothing for it): lane d reads
+                // the tag of the cell d diagonal moves on (from the window,
+                // across lanes with ds_bpermute); the moves up to the first
+                // lane that does not hold a diagonal tag inside the window
+                // are all diagonal.
+                const int c = (l << kLogC) + k;
+                const int cd = c - lane;
+                const int ld = cd >> kLogC, kd = cd & (C - 1);
+                const int td = t - lane - (l - ld);
+                const bool inside = cd >= 0 && ld >= lmin && td >= tmin && td >= 0 && i - lane >= 1 && j - lane >= 1;
+                const int xd = ((td >> 4) << (4 + kLogC)) + (ld << kLogC) + kd + xo;
+                uint32_t wd = 0;
+#pragma unroll
+                for (int r = 0; r < C; ++r) {
+                    const uint32_t v = (uint32_t)__builtin_amdgcn_ds_bpermute((xd & 63) << 2, (int)win[r]);
+                    wd = ((xd >> 6) == r) ? v : wd;
+                }
+                const uint32_t tagd = inside ? (wd >> (2 * (td & 15))) & 3u : 0u;
+                const uint64_t stop = __builtin_amdgcn_ballot_w64(tagd != 3u);
+                const int run = stop ? __builtin_ctzll(stop) : kWave;
+                if (run > 0) {
+                    const int q0 = (int)(q & 63);
+                    const int e1 = min(kWave, q0 + run);
+                    buf = (lane >= q0 && lane < e1) ? 1u : buf;
+                    if (e1 == kWave) rev[(q & ~(int64_t)63) + lane] = (uint8_t)buf;
+                    const int rest = q0 + run - kWave;
+                    if (rest > 0) buf = (lane < rest) ? 1u : buf;
+                    q += run;
+                    i -= run;
+                    j -= run;
+                    const int cn = c - run;
+                    const int ln = cn >> kLogC;
+                    t -= run + (l - ln);
+                    l = ln;
+                    k = cn & (C - 1);
+                    if ((i <= 0) | (j <= 0) | (t < tmin) | (l < lmin)) break;
+                }
+            }
             const int x = ((t >> 4) << (4 + kLogC)) + (l << kLogC) + k + xo;
             if ((x >> 6) != cur_r) {
                 cur_r = x >> 6;
@@ -569,6 +612,7 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
             ++q;
             if (__builtin_expect((q & 63) == 0, 0)) rev[q - 64 + lane] = (uint8_t)buf;
             const int up = tag >> 1, left = tag & 1;
+            diag = tag == 3;
             const int kk = k - left;
             const int wrap = (int)((uint32_t)kk >> 31);
             i -= up;
