@@ -112,6 +112,15 @@ int nw_sync(void *stream);
  * reported.  polls < 0 is NW_EINVAL. */
 int nw_set_wait_limit(int32_t polls);
 
+/* Tuning hook of nw_align's traceback (multi-wave engine, n >= 512): paths of
+ * at most `moves` moves (m + n) are walked back from (m, n) by one wave;
+ * longer ones by every strip in parallel from guessed entry rows, then
+ * merged (Sec. 3.1 and 4.1: the traceback follows the stored directions from
+ * the last cell).  Both give the same path.  Default 4096; 0 restores the
+ * default, 1 sends every such pair to the parallel walk.  Applies to calls
+ * queued afterwards; moves < 0 is NW_EINVAL. */
+int nw_set_walk_limit(int64_t moves);
+
 /* Flags. */
 #define NW_SCORE_ONLY 0x1u /* no traceback: paths, path_off, path_len may be NULL */
 /* NW_GRAPH (nw_align_batch, nw_align_batch_banded, nw_align_batch_learned):

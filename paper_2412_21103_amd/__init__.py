@@ -21,7 +21,7 @@ __all__ = [
     "profile_end", "align_batch_banded", "banded_workspace_size", "Mlp", "MLP_INPUTS",
     "MLP_PARAMS", "mlp_features", "mlp_forward", "mlp_widths", "band_labels", "path_labels", "mlp_train_step",
     "mlp_train_epoch", "align_batch_learned", "learned_workspace_size", "autotune", "init", "sync",
-    "set_wait_limit", "align_noalloc", "align_noalloc_fits", "sweep_costs", "set_sweep_costs",
+    "set_wait_limit", "set_walk_limit", "align_noalloc", "align_noalloc_fits", "sweep_costs", "set_sweep_costs",
     "autotune_cached",
 ]
 
@@ -114,6 +114,8 @@ def lib():
         L.nw_sync.restype = ctypes.c_int
         L.nw_set_wait_limit.argtypes = [_i32]
         L.nw_set_wait_limit.restype = ctypes.c_int
+        L.nw_set_walk_limit.argtypes = [ctypes.c_int64]
+        L.nw_set_walk_limit.restype = ctypes.c_int
         L.nw_release_caches.restype = None
         L.nw_sweep_costs.argtypes = [_vp, _vp]
         L.nw_set_sweep_costs.argtypes = [_vp]
@@ -596,6 +598,13 @@ def set_wait_limit(polls: int):
     """nw_set_wait_limit: polls a bounded wait between waves makes before it
     gives up (0 restores the default).  A testing hook for the fault path."""
     _check(lib().nw_set_wait_limit(int(polls)), "nw_set_wait_limit")
+
+
+def set_walk_limit(moves: int):
+    """nw_set_walk_limit: nw_align (from 512 columns) walks paths of at most
+    `moves` moves back with one wave and longer ones strip-parallel (0
+    restores the default, 1 sends every such pair to the parallel walk)."""
+    _check(lib().nw_set_walk_limit(int(moves)), "nw_set_walk_limit")
 
 
 def profile_begin():

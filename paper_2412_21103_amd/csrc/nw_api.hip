@@ -38,6 +38,7 @@ FaultWords& fault_words() {
     return f;
 }
 std::atomic<int32_t> g_spin_limit{kDefaultSpinLimit};
+std::atomic<int64_t> g_walk_limit{kDefaultWalkLimit};
 
 // One pinned host allocation per process, made on first use.
 void init_fault_words() {
@@ -75,6 +76,7 @@ int device_info(DeviceInfo* out, bool may_allocate) {
     FaultWords& F = fault_words();
     out->fault = (F.dev && dev < kMaxFaultDevices) ? F.dev + dev : nullptr;
     out->spin_limit = g_spin_limit.load();
+    out->walk_limit = g_walk_limit.load();
     if (!out->supported) return NW_ENOTSUP;
     // a fault reported by earlier work on this device surfaces here, once
     return take_fault(dev) ? NW_EDEVICE : NW_OK;
@@ -282,6 +284,12 @@ int nw_sync(void* stream) {
 int nw_set_wait_limit(int32_t polls) {
     if (polls < 0) return NW_EINVAL;
     g_spin_limit.store(polls == 0 ? kDefaultSpinLimit : polls);
+    return NW_OK;
+}
+
+int nw_set_walk_limit(int64_t moves) {
+    if (moves < 0) return NW_EINVAL;
+    g_walk_limit.store(moves == 0 ? kDefaultWalkLimit : moves);
     return NW_OK;
 }
 

@@ -27,6 +27,7 @@ struct DeviceInfo {
     bool supported;
     uint32_t* fault;     // device view of this device's fault word (nullptr before nw_init)
     int32_t spin_limit;  // polls before a boundary wait gives up
+    int64_t walk_limit;  // nw_align: longest path (m + n) traced back by one wave
 };
 // Fills *out for the current device.  With may_allocate (the default) the
 // pinned fault words are set up on first use; without, a library that was
@@ -38,6 +39,10 @@ int device_info(DeviceInfo* out, bool may_allocate = true);
 // it, milliseconds for 65,536 columns), about 0.4 s of LDS polls or a few
 // seconds of L2 polls.
 constexpr int32_t kDefaultSpinLimit = 1 << 22;
+
+// Default longest path (m + n moves) that nw_align traces back with one wave
+// instead of the per-strip parallel walk.
+constexpr int64_t kDefaultWalkLimit = 1 << 12;
 
 // Device faults (a bounded wait that gave up, a corrupt direction tag) are
 // reported by the kernels in a word of pinned host memory per device; the

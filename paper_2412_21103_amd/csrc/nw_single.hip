@@ -11,18 +11,23 @@
 // (CoopIO), so the fill runs as one anti-diagonal front across all strips,
 // each strip a fixed lag behind its left neighbour.
 //
-// Traceback.  A single serial walk from (m, n) would take one dependent
-// lookup per move (about 130k moves for a 65,536-base pair).  Instead every
-// strip first walks its own part of the path in parallel (k_tb_spec), starting
-// from a guessed entry row: the row near the diagonal where the strip's right
-// boundary column (left behind by the fill) scores best.  The strip notes, for each of its
-// columns, the rows its walk visited and the move index at which it entered
-// the column.  One wave then chains the strips from the last to the first
-// (k_tb_fix): the true path enters strip s where it left strip s+1; if that
-// cell lies on strip s's walk, the rest of the strip is that walk's suffix
-// (walks from the same cell are identical), otherwise the wave walks from the
-// true entry until it meets the speculative walk or leaves the strip.  A last
-// pass (k_tb_emit) writes every strip's segment, reversed, at its offset.
+// Traceback.  Paths of up to a few thousand moves are walked back by one wave
+// (k_tb_walk).  For longer ones one serial walk from (m, n) would take one dependent lookup per
+// move (about 130k moves for a 65,536-base pair), so every strip first walks
+// its own part of the path in parallel (k_tb_spec), starting from a guessed
+// entry row: the row near the diagonal where the strip's right boundary
+// column (left behind by the fill) scores best.  The strip notes, for each of
+// its columns, the rows its walk visited and the move index at which it
+// entered the column.  Then every strip at once (k_tb_merge) takes as its true
+// entry the exit row of the next strip's speculative walk: if that cell lies
+// on its own walk, the rest of the strip is that walk's suffix (walks from the
+// same cell are identical), otherwise the strip walks from the entry until it
+// meets its speculative walk.  If every strip meets it, each segment's offset
+// follows from a prefix sum (k_tb_fix) and a last pass (k_tb_emit) writes
+// every strip's segment, reversed, at its offset.  If one leaves its strip
+// without meeting it (parallel co-optimal paths that never touch, common for
+// unrelated sequences), the entries are not known at once and k_tb_fix walks
+// the whole path with one wave as k_tb_walk does.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -179,7 +184,8 @@ struct TbArgs {
     int32_t* info;       // per strip: kInfoHead ints, then lo[], hi[], idx[] per column
     int64_t info_stride;
     int32_t* fix;        // per strip: rw_len, seg_from, total_len, offset
-    int32_t* summary;    // [0] tail (vertical moves at column 0), [1] path length, [2] error
+    int32_t* summary;    // [0] tail (vertical moves at column 0), [1] path length, [2] error, [4] a re-walk
+                         // left its strip, [5] a corrupt tag in k_tb_merge, [6] k_tb_fix wrote the path
     const int32_t* err;  // fill failure flag
     uint8_t* path;
     int64_t* path_len;
@@ -346,8 +352,8 @@ __device__ bool rewalk(const TbArgs& T, int s, int e, int32_t (*col)[kWave * C],
 // speculative walk, the true path leaves each strip where that walk leaves
 // it, so the entry row of strip s is the speculative exit row of strip s + 1
 // and no strip has to wait for another.  A re-walk that leaves its strip
-// without meeting the walk breaks that assumption: the flag it raises sends
-// k_tb_fix down the sequential chain instead.
+// without meeting the walk breaks that assumption: the flag it raises makes
+// k_tb_fix walk the whole path with one wave instead.
 template <int C>
 __global__ __launch_bounds__(kCoopThreads) void k_tb_merge(TbArgs T) {
     constexpr int kCols = kWave * C;
@@ -380,77 +386,63 @@ __global__ __launch_bounds__(kCoopThreads) void k_tb_merge(TbArgs T) {
     }
 }
 
-// Offsets of every strip's segment; when some re-walk left its strip without
-// meeting the speculative walk, one wave first chains the strips from the
-// last to the first instead.
+// One wave walks the whole path back from (m, n) on the stored directions
+// (walk_back: scalar state, a register window, diagonal runs in one step)
+// into the walk-move buffer, then writes it out in forward order.  Returns
+// the number of moves, or -1 for a corrupt tag.
+template <int C>
+__device__ int64_t walk_whole(const TbArgs& T) {
+    const int64_t len = walk_back<C>(T.dirs, T.m, T.n, T.G, nullptr, T.seg);
+    if (len < 0 || len > T.cap) return -1;
+    // the moves were written by other lanes of this wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int64_t x = lane_id(); x < len; x += kWave) T.path[x] = T.seg[len - 1 - x];
+    return len;
+}
+
+// Paths of up to a few thousand moves: the one-wave walk is shorter than the
+// per-strip walks, their merge and their placement together.
+template <int C>
+__global__ __launch_bounds__(kWave) void k_tb_walk(TbArgs T) {
+    int64_t len = -3;  // fill failure
+    if (__hip_atomic_load(T.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) len = walk_whole<C>(T);
+    if (lane_id() == 0) {
+        if (len < 0) {
+            T.score[0] = INT32_MIN;
+            T.path_len[0] = len == -3 ? -3 : -2;
+            report_fault(T.fault);
+        } else {
+            T.path_len[0] = len;
+        }
+    }
+}
+
+// Offsets of every strip's segment.  When some re-walk left its strip without
+// meeting the speculative walk, the strips' entries are not known at once;
+// one wave then walks the whole path back instead (as k_tb_walk) and writes
+// it out itself.
 template <int C>
 __global__ __launch_bounds__(kWave) void k_tb_fix(TbArgs T) {
-    constexpr int kCols = kWave * C;
-    __shared__ uint32_t win_lds[kWave * C];
-    __shared__ int32_t col_lds[3][kCols];
     const int lane = lane_id();
     if (__hip_atomic_load(T.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         if (lane == 0) T.summary[2] = 3;
         return;
     }
-    DirWindow<C> win(T.dirs, T.G, win_lds);
-    int e = T.m;     // entry row of the current strip
-    int error = 0;
-    if (__hip_atomic_load(T.summary + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        // k_tb_merge has placed every strip: the path reaches column 0 where
-        // strip 0's speculative walk does
-        error = __hip_atomic_load(T.summary + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        e = T.info[2];
-    } else {
-        // headers arrive 64 strips at a time: lane q holds strip (base - q)
-        int base = T.nstrips - 1;
-        int32_t h_len = 0, h_start = 0, h_exit = 0, h_lo = 0, h_hi = 0, h_bad = 0;
-        auto load_chunk = [&](int b) {
-            const int sq = b - lane;
-            if (sq >= 0) {
-                const int32_t* rec = T.info + (int64_t)sq * T.info_stride;
-                h_len = rec[0];
-                h_start = rec[1];
-                h_exit = rec[2];
-                h_lo = rec[3];
-                h_hi = rec[4];
-                h_bad = rec[5];
-            }
-        };
-        load_chunk(base);
-        for (int s = T.nstrips - 1; s >= 0; --s) {
-            if (base - s >= kWave) {
-                base = s;
-                load_chunk(base);
-            }
-            const int ql = base - s;
-            const int len = __builtin_amdgcn_readlane(h_len, ql);
-            const int start = __builtin_amdgcn_readlane(h_start, ql);
-            const int sexit = __builtin_amdgcn_readlane(h_exit, ql);
-            const int loR = __builtin_amdgcn_readlane(h_lo, ql);
-            const int hiR = __builtin_amdgcn_readlane(h_hi, ql);
-            error |= __builtin_amdgcn_readlane(h_bad, ql);
-            int rw_len = 0, seg_from = 0, exit_row = sexit;
-            if (s == T.nstrips - 1) {
-                seg_from = 0;
-            } else if (hiR >= 0 && loR <= e && e <= hiR) {
-                seg_from = start - e;
-            } else {
-                // walk from the true entry until the speculative walk is met
-                int rexit = 0;
-                if (!rewalk<C>(T, s, e, col_lds, win, rw_len, seg_from, rexit, error)) {
-                    seg_from = len;
-                    exit_row = rexit;
-                }
-            }
-            int32_t* f = T.fix + 4 * (int64_t)s;
-            f[0] = rw_len;
-            f[1] = seg_from;
-            f[2] = rw_len + (len - seg_from);
-            e = exit_row;
+    if (__hip_atomic_load(T.summary + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        const int64_t len = walk_whole<C>(T);
+        if (lane == 0) {
+            T.summary[2] = len < 0 ? 1 : 0;
+            T.summary[6] = 1;  // the path is out
+            if (len >= 0) T.path_len[0] = len;
         }
+        return;
     }
-    // e is now the row at which the path reaches column 0: that many vertical
+    // k_tb_merge has placed every strip: the path reaches column 0 where
+    // strip 0's speculative walk does
+    int error = __hip_atomic_load(T.summary + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int e = T.info[2];
+    // e is the row at which the path reaches column 0: that many vertical
     // moves come first in forward order, then strips 0, 1, ... in turn
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -490,6 +482,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_tb_emit(TbArgs T) {
         }
         return;
     }
+    if (T.summary[6] != 0) return;  // k_tb_fix walked and wrote the whole path
     if (s == 0) {
         const int tail = T.summary[3];
         for (int x = lane; x < tail; x += kWave) T.path[x] = 2;
@@ -690,6 +683,11 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
         T.score = score;
         T.cap = m + n;
         const unsigned blocks = (unsigned)((L.nstrips + kCoopWaves - 1) / kCoopWaves);
+        if (m + n <= di.walk_limit) {
+            ProfScope ps("nw_tb_walk", st);
+            hipLaunchKernelGGL(k_tb_walk<kCoopC>, dim3(1), dim3(kWave), 0, st, T);
+            return hipGetLastError() == hipSuccess ? NW_OK : NW_EDEVICE;
+        }
         {
             ProfScope ps("nw_tb_spec", st);
             hipLaunchKernelGGL(k_tb_spec<kCoopC>, dim3(blocks), dim3(kCoopThreads), 0, st, T);

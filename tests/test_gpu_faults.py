@@ -42,11 +42,13 @@ def _exact(a, b, s, path, plen):
     return int(s.item()) == s_ref and k == len(p_ref) and path[:k].cpu().numpy().tolist() == p_ref.tolist()
 
 
-def test_wait_limit_reports_fault_and_recovers():
+@pytest.mark.parametrize("walk", [1 << 30, 1], ids=["one_wave_walk", "strip_parallel_walk"])
+def test_wait_limit_reports_fault_and_recovers(walk):
     a, b = _pair(1, 4096)  # 32 strips on 8 blocks: waits inside blocks and between them
     da, db = dev_u8(a), dev_u8(b)
-    say("faults: nw_align with a wait limit of one poll")
+    say(f"faults: nw_align with a wait limit of one poll, walk limit {walk}")
     nwp.set_wait_limit(1)
+    nwp.set_walk_limit(walk)
     try:
         s, path, plen = nwp.align(da, db)
         with pytest.raises(nwp.NWError) as e:
@@ -62,12 +64,14 @@ def test_wait_limit_reports_fault_and_recovers():
         with pytest.raises(nwp.NWError) as e:
             nwp.align(da, db)
         assert e.value.status == -4
+        nwp.set_wait_limit(0)
+        say("faults: default wait limit again")
+        s, path, plen = nwp.align(da, db)
+        nwp.sync()
+        assert _exact(a, b, s, path, plen)
     finally:
         nwp.set_wait_limit(0)
-    say("faults: default limit again")
-    s, path, plen = nwp.align(da, db)
-    nwp.sync()
-    assert _exact(a, b, s, path, plen)
+        nwp.set_walk_limit(0)
 
 
 def test_wait_limit_cooptimal_teams():
@@ -95,6 +99,7 @@ def test_wait_limit_cooptimal_teams():
 
 def test_set_wait_limit_rejects_negative():
     assert nwp.lib().nw_set_wait_limit(-1) == -1
+    assert nwp.lib().nw_set_walk_limit(-1) == -1
 
 
 def test_align_graph_replays_see_new_inputs():

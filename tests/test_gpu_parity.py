@@ -132,9 +132,19 @@ def test_allpairs_matches_oracle():
     assert (M == M.T).all() and (np.diag(M) == lens).all()
 
 
-def test_cooperative_single_pair_shapes():
+@pytest.fixture
+def walk_limit(request):
+    import paper_2412_21103_amd as nwp
+    nwp.set_walk_limit(request.param)
+    yield request.param
+    nwp.set_walk_limit(0)
+
+
+@pytest.mark.parametrize("walk_limit", [1 << 30, 1], indirect=True, ids=["one_wave_walk", "strip_parallel_walk"])
+def test_cooperative_single_pair_shapes(walk_limit):
     # one pair with n >= 512 runs on many waves; cover tiny m, strip-multiple
-    # and ragged n, and long m
+    # and ragged n, and long m; every path traced back by one wave, and every
+    # path by the strip-parallel walk
     rng = np.random.default_rng(24)
     for m, n in [(1, 512), (2, 4096), (17, 640), (100, 5000), (3000, 2999), (4097, 4096),
                  (700, 8193), (9000, 1100)]:
@@ -142,12 +152,13 @@ def test_cooperative_single_pair_shapes():
         b = mutate(rng, random_seq(rng, n), 0.0) if m < 50 else mutate(rng, a, 0.12)[:n]
         if len(b) < n:
             b = np.concatenate([b, random_seq(rng, n - len(b))])
-        say(f"coop m={m} n={n}")
+        say(f"coop m={m} n={n} walk limit {walk_limit}")
         check_pair(a, b, P, "coop")
 
 
-def test_cooperative_traceback_both_chains():
-    # The long-pair traceback places every strip's segment at once when each
+@pytest.mark.parametrize("walk_limit", [1], indirect=True)
+def test_cooperative_traceback_both_chains(walk_limit):
+    # The strip-parallel traceback places every strip's segment at once when each
     # re-walk from a strip's true entry meets that strip's speculative walk,
     # and falls back to chaining the strips one by one when one does not.
     # Periodic and unrelated sequences have parallel co-optimal paths that
