@@ -49,6 +49,10 @@ BAND_COUNTERS = os.path.join(ROOT, "profiles", "batch_banded_band_batch_8192.cou
 BAND_VALU = os.path.join(ROOT, "profiles", "batch_banded_band_batch_8192.valu.json")
 BATCH_COUNTERS = os.path.join(ROOT, "profiles", "batch_batch_4096.counters.json")
 BATCH_VALU = os.path.join(ROOT, "profiles", "batch_batch_4096.valu.json")
+COOP_VALU = os.path.join(ROOT, "profiles", "fill_coop_long_pair_65536.valu.json")
+ALLPAIRS_VALU = os.path.join(ROOT, "profiles", "batch_allpairs_512.valu.json")
+COUNT_VALU = os.path.join(ROOT, "profiles", "count_cooptimal_batch_4096_counts.valu.json")
+COUNT_SOURCES = ["paper_2412_21103_amd/csrc/nw_common.h", "paper_2412_21103_amd/csrc/nw_coopt.hip"]
 
 
 def kernel_hash(sources) -> str:
@@ -533,6 +537,8 @@ def bench_allpairs(args):
     ms, prof = timed_steps(step, args, torch.cuda.synchronize)
     k = prof.get("nw_allpairs")
     roof = alu_roofline("nw_allpairs", cells, k[1] / k[0] if k else None, 2)
+    if roof:
+        roof["valu"] = valu_record(ALLPAIRS_VALU, BAND_SOURCES)
     cpu = exact = None
     if not args.no_cpu_baseline:
         import oracle
@@ -598,6 +604,8 @@ def bench_cooptimal(args):
     ms, prof = timed_steps(step, args, torch.cuda.synchronize)
     k = prof.get("nw_cooptimal")
     roof = alu_roofline("nw_cooptimal", cells, k[1] / k[0] if k else None, COUNT_OPS_PER_CELL)
+    if roof:
+        roof["valu"] = valu_record(COUNT_VALU, COUNT_SOURCES)
     # the first four paths of every pair, same pairs
     kp = 4
     print(f"bench: counts + first {kp} paths", file=sys.stderr, flush=True)
@@ -770,12 +778,30 @@ def bench_long_pair(args, length=65536, oracle_check=True):
     gpu_path = path[:k].cpu().numpy()
     fill = prof.get("nw_fill_coop")
     fill_ms = fill[1] / fill[0] if fill else None
-    tb = [prof[x] for x in ("nw_tb_spec", "nw_tb_merge", "nw_tb_fix", "nw_tb_emit") if x in prof]
+    tb = [prof[x] for x in ("nw_tb_walk", "nw_tb_spec", "nw_tb_merge", "nw_tb_fix", "nw_tb_emit") if x in prof]
     walk_ms = sum(v[1] / v[0] for v in tb) if tb else None
     roofline = alu_roofline("nw_fill_coop", cells, fill_ms, FILL_OPS_PER_CELL)
+    pipeline = None
     if roofline:
         roofline["traffic"] = traffic_record(COOP_COUNTERS, COOP_SOURCES)
         roofline["frac_at_7_ops_per_cell"] = round(7 * cells / (fill_ms * 1e-3) / 1e12 / PEAK_INT32_TOPS, 4)
+        valu = valu_record(COOP_VALU, COOP_SOURCES)
+        roofline["valu"] = valu
+        # The fill is a pipeline of 128-column strips, each starting at least
+        # one hop (64 steps of lane skew + one 32-row group) behind the strip
+        # to its left: rows + 63 + (strips - 1) * 96 steps of one strip.  At
+        # the measured VALU instructions per cell, a step of 2 columns per
+        # lane issues in instr/cell * 2 * 4 cycles; the ratio of that bound
+        # to the fill time is the fill's fraction of its critical path.
+        strips = (n + 127) // 128
+        steps = m + 63 + (strips - 1) * 96
+        pipeline = {"strips": strips, "critical_path_steps": steps,
+                    "measured_ns_per_step": round(fill_ms * 1e6 / steps, 2)}
+        if valu and valu.get("valu_lane_instr_per_cell"):
+            issue_ns = valu["valu_lane_instr_per_cell"] * 2 * 4 / 2.4
+            pipeline.update({"issue_bound_ns_per_step": round(issue_ns, 2),
+                             "critical_path_bound_ms": round(steps * issue_ns * 1e-6, 4),
+                             "critical_path_frac": round(steps * issue_ns * 1e-6 / fill_ms, 4)})
     cpu = exact = None
     if oracle_check and not args.no_cpu_baseline:
         import oracle
@@ -787,13 +813,11 @@ def bench_long_pair(args, length=65536, oracle_check=True):
         cpu = {"value": round(cells / (c1 - c0) / 1e9, 4), "unit": "GCUPS", "cores": 1, "kind": "oracle",
                "sample": f"the whole {m} x {n} pair, score + traceback, two score rows + "
                          f"a direction byte per cell, {round(c1 - c0, 2)} s", **_cpu_info()}
-    # the anti-diagonal ramp: strip s starts a hop behind strip s-1, so the
-    # fill takes about rows + (strips - 1) * hop steps of one strip
     config = {"workload": f"long_pair_{length}", "m": m, "n": n, "mutation_rate": 0.10,
               "scoring": list(nwp.PAPER_SCORING), "traceback": True, **_stats(ms),
               "fill_ms": round(fill_ms, 4) if fill_ms else None,
               "traceback_ms": round(walk_ms, 4) if walk_ms else None,
-              "bit_exact_vs_oracle": exact}
+              "fill_pipeline": pipeline, "bit_exact_vs_oracle": exact}
     return cells / (wall * 1e-3) / 1e9, wall, config, roofline, cpu
 
 
