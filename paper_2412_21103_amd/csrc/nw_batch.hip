@@ -273,6 +273,130 @@ __device__ __forceinline__ int32_t fill_pair(const KArgs& A, const uint8_t* pa, 
     return __builtin_amdgcn_readlane(vlast, lsel);
 }
 
+// Boundary IO of a strip swept in row ranges of both domains (fill_mixed):
+// the boundary column stays in the W domain; a range swept with directions
+// converts what it reads (V = 4W + 1, -infinity kept at kNegV without
+// overflow) and what it writes (W = V >> 2).
+struct MixIO : PlainIO {
+    bool vdom = false;
+    __device__ __forceinline__ int32_t value(Slot x, int r) const {
+        if (r > m) return beyond;
+        if (!bin) return vinit;
+        if (r0 + r > in_hi) return beyond;
+        return vdom ? max(4 * max(x, kNegW) + 1, kNegV) : x;
+    }
+    __device__ __forceinline__ void store(int r, int32_t v, bool want) const {
+        int32_t* dst = (want && bout != nullptr) ? bout + r0 + r : spare;
+        *dst = vdom ? (v >> 2) : v;
+    }
+};
+
+// One pass over band(w) (or the full grid) that records directions only in
+// the rows band(w2) covers in each strip, w2 <= w.  Each strip is swept in up
+// to three row ranges -- score-only above band(w2)'s rows, with directions
+// inside them, score-only below -- and the lanes carry their values from one
+// range to the next (converted between the W and V domains).  The scores are
+// those of band(w); the directions are band(w)'s at the cells of band(w2)'s
+// staircase, stored with band(w2)'s layout (*G_out groups per strip), so a
+// walk that stays in those rows follows band(w)'s traceback.  Returns W at
+// (m, n); *cells_so gets the cells swept without directions.
+template <int C, bool WIDE>
+__device__ __forceinline__ int32_t fill_pair_mixed(const KArgs& A, const uint8_t* pa, const uint8_t* pb, int m,
+                                                   int n, uint32_t shift, bool full, int w, int w2, int32_t* bnd,
+                                                   int32_t* spare, uint32_t* dirs, uint32_t* lds, int* G_out,
+                                                   int64_t* cells, int64_t* cells_so) {
+    constexpr int kCols = kWave * C;
+    const int lo_d = min(0, n - m), hi_d = max(0, n - m);
+    const int nstrips = (n + kCols - 1) / kCols;
+    const int G2 = groups_for_rows(min(m, kCols + hi_d - lo_d + 2 * w2));
+    *G_out = G2;
+    int32_t last = 0;
+    bool last_v = false;
+    int prev_lo = 1, prev_hi = m;
+    int64_t swept = 0, swept_so = 0;
+    for (int s = 0; s < nstrips; ++s) {
+        const int j0 = s * kCols;
+        const int cols = min(kCols, n - j0);
+        const int rs = full ? 1 : max(1, j0 + 1 - hi_d - w);
+        const int re = full ? m : min(m, j0 + kCols - lo_d + w);
+        const int rd0 = max(rs, j0 + 1 - hi_d - w2);   // rows with directions: rd0 .. rd1
+        const int rd1 = min(re, j0 + kCols - lo_d + w2);
+        const int ksel = (n - 1 - j0) % C;
+        // ranges: [rs, rd0-1] score-only, [rd0, rd1] with directions, [rd1+1, re] score-only
+        const int ra[3] = {rs, rd0, rd1 + 1};
+        const int rb[3] = {rd0 - 1, rd1, re};
+        // the previous strip's last column one row above each range (W), read
+        // before the ranges of this strip overwrite the boundary
+        int32_t dgw[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int r0 = ra[q] - 1;
+            dgw[q] = 0;
+            if (s > 0 && r0 > 0) dgw[q] = (r0 >= prev_lo && r0 <= prev_hi) ? bnd[r0] : kNegW;
+        }
+        // lanes start from the row above the strip's region: the grid's first
+        // row, or -infinity
+        int32_t st[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) st[k] = (rs == 1) ? 0 : kNegW;
+        bool st_v = false;  // domain of st
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int rows = rb[q] - ra[q] + 1;
+            if (rows <= 0) continue;
+            const bool vd = (q == 1);
+            if (vd != st_v) {
+#pragma unroll
+                for (int k = 0; k < C; ++k) st[k] = vd ? max(4 * max(st[k], kNegW) + 1, kNegV) : (st[k] >> 2);
+                st_v = vd;
+            }
+            const int r0 = ra[q] - 1;
+            MixIO io;
+            io.bin = s == 0 ? nullptr : bnd;
+            io.bout = s == nstrips - 1 ? nullptr : bnd;
+            io.spare = spare;
+            io.m = rows;
+            io.vinit = vd ? 1 : 0;
+            io.r0 = r0;
+            io.in_hi = (s == 0) ? m : prev_hi;
+            io.beyond = full ? 0 : (vd ? kNegV : kNegW);
+            io.vdom = vd;
+            const int32_t dg0 = vd ? max(4 * max(dgw[q], kNegW) + 1, kNegV) : dgw[q];
+            if (vd) {
+                last = sweep_strip<C, true, WIDE, MixIO, true>(pa + r0, rows, pb, n, j0, A.kdm, A.kdx, shift, 0, dg0,
+                                                               io, dirs + (size_t)s * G2 * kWave * C, lds, ksel, st);
+            } else {
+                last = sweep_strip<C, false, WIDE, MixIO, true>(pa + r0, rows, pb, n, j0, A.kdm_w, A.kdx_w, shift, 0,
+                                                                dg0, io, nullptr, lds, ksel, st);
+                swept_so += (int64_t)rows * cols;
+            }
+            last_v = vd;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        prev_lo = rs;
+        prev_hi = re;
+        swept += (int64_t)(re - rs + 1) * cols;
+    }
+    *cells += swept;
+    *cells_so += swept_so;
+    const int lsel = (n - 1 - (nstrips - 1) * kCols) / C;
+    const int32_t v = __builtin_amdgcn_readlane(last, lsel);
+    return last_v ? (v >> 2) : v;
+}
+
+template <bool WIDE>
+__device__ __forceinline__ int32_t fill_mixed(int C, const KArgs& A, const uint8_t* pa, const uint8_t* pb, int m,
+                                              int n, uint32_t shift, bool full, int w, int w2, int32_t* bnd,
+                                              int32_t* spare, uint32_t* dirs, uint32_t* lds, int* G, int64_t* cells,
+                                              int64_t* cells_so) {
+    if (C == 8)
+        return fill_pair_mixed<8, WIDE>(A, pa, pb, m, n, shift, full, w, w2, bnd, spare, dirs, lds, G, cells, cells_so);
+    if (C == 4)
+        return fill_pair_mixed<4, WIDE>(A, pa, pb, m, n, shift, full, w, w2, bnd, spare, dirs, lds, G, cells, cells_so);
+    return fill_pair_mixed<2, WIDE>(A, pa, pb, m, n, shift, full, w, w2, bnd, spare, dirs, lds, G, cells, cells_so);
+}
+
 // Band height (rows per strip) of band(w) for a C-column sweep.
 __device__ __forceinline__ int band_height(int C, int m, int n, int w) {
     const int dlt = n > m ? n - m : m - n;
@@ -309,6 +433,13 @@ __device__ __forceinline__ int32_t fill_any(int C, const KArgs& A, const uint8_t
     if (C == 8) return fill_pair<8, DIRS, WIDE>(A, pa, pb, m, n, shift, full, w, bnd, spare, dirs, lds, G, cells);
     if (C == 4) return fill_pair<4, DIRS, WIDE>(A, pa, pb, m, n, shift, full, w, bnd, spare, dirs, lds, G, cells);
     return fill_pair<2, DIRS, WIDE>(A, pa, pb, m, n, shift, full, w, bnd, spare, dirs, lds, G, cells);
+}
+
+__device__ __forceinline__ int64_t walk_checked(int C, const uint32_t* dirs, int m, int n, int G, uint8_t* rev,
+                                                int band_hi, int span_lo) {
+    if (C == 8) return walk_back<8, true>(dirs, m, n, G, nullptr, rev, band_hi, span_lo);
+    if (C == 4) return walk_back<4, true>(dirs, m, n, G, nullptr, rev, band_hi, span_lo);
+    return walk_back<2, true>(dirs, m, n, G, nullptr, rev, band_hi, span_lo);
 }
 
 __device__ __forceinline__ int64_t walk_any(int C, const uint32_t* dirs, int m, int n, int G, uint32_t* lds,
@@ -379,6 +510,8 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
             bool full = true;
             int w = 0;
             int C = 8;
+            int w_dirs = -1;  // >= 0: the last pass recorded directions only in band(w_dirs)
+            int passes = 0;
             if constexpr (BANDED) {
                 // certified band: sweep band(w); if the region's score does not
                 // beat the best score any path leaving band(w) can reach, widen the
@@ -394,7 +527,6 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                 const int64_t fb_num = (int64_t)A.frac_1024 * m - 1024 * (2 * kWave + dlt) - 1;
                 const int64_t w_fb = fb_num >= 0 ? fb_num / 2048 : -1;
                 if (w < mn && w_fb >= 0 && w > w_fb) w = (int)w_fb;
-                int passes = 0;
                 int c_min = 2;
                 // With widening, a first pass that does not certify serves only to
                 // find the region's score, so it runs score-only (no direction
@@ -402,6 +534,7 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                 // directions.  Doubled passes all record directions.
                 bool probe = DIRS && !A.band_doubling;
                 bool certified_first = false;
+                int mixed_next = -1;  // after a failed first pass: record directions only in its band
                 for (;;) {
                     // a pass after a failed one is certain to certify (unless
                     // doubling), so it takes the full grid only once the band
@@ -412,7 +545,16 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                     C = uniform(pick_cols(A, m, n, full, w, c_min));
                     const bool score_only = probe && !full;
                     int32_t v;
-                    if (score_only) {
+                    w_dirs = -1;
+                    if (DIRS && mixed_next >= 0) {
+                        // the path most likely lies near the failed first pass's
+                        // band: directions in band(1.5 w0 + 16), scores elsewhere
+                        w_dirs = min(w, mixed_next + mixed_next / 2 + 16);
+                        mixed_next = -1;
+                        v = fill_mixed<WIDE>(C, A, P.a, P.b, m, n, shift, full, w, w_dirs, bnd, spare, dirs, lds, &G,
+                                             &cells, &cells_so_out);
+                        score = v + A.gap * (m + n);
+                    } else if (score_only) {
                         const int64_t before = cells;
                         v = fill_any<false, WIDE>(C, A, P.a, P.b, m, n, shift, false, w, bnd, spare, nullptr, lds, &G,
                                                   &cells);
@@ -445,6 +587,8 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                     // least S_R and the next pass certifies.
                     const int64_t num = (int64_t)A.cd * (mn - 1) + (int64_t)A.gap * (dlt + 2) - score;
                     const int64_t den = (int64_t)A.cd - 2 * (int64_t)A.gap;
+                    if (score_only) mixed_next = w;
+                    w_dirs = -1;
                     w = (int)min((int64_t)mn, max((int64_t)w + 1, num / den + 1));
                     c_min = C;
                 }
@@ -461,7 +605,35 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
             }
             if constexpr (DIRS && !ALLPAIRS) {
                 const int band_hi = full ? (1 << 30) : max(0, n - m) + w;
-                int64_t len = walk_any(C, dirs, m, n, G, lds, rev, band_hi);
+                int64_t len;
+                if (BANDED && w_dirs >= 0) {
+                    // directions exist only in band(w_dirs)'s rows: a walk that
+                    // would leave them stops, and band(w) is swept again with
+                    // directions everywhere
+                    len = walk_checked(C, dirs, m, n, G, rev, max(0, n - m) + w_dirs, w_dirs - min(0, n - m));
+                    while (len == -3) {
+                        // the walk left them: the same pass again with directions in
+                        // a band four times as wide, or everywhere once that covers
+                        // band(w)
+                        fence_wave_memory();
+                        ++passes;
+                        st_out = (st_out & ~0x3Eu) | ((uint32_t)min(passes - 1, 31) << 1);
+                        w_dirs = 4 * w_dirs + 64;
+                        if (w_dirs >= w) {
+                            fill_any<DIRS, WIDE>(C, A, P.a, P.b, m, n, shift, full, w, bnd, spare, dirs, lds, &G,
+                                                 &cells);
+                            cells_out = cells;
+                            len = walk_any(C, dirs, m, n, G, lds, rev, band_hi);
+                            break;
+                        }
+                        fill_mixed<WIDE>(C, A, P.a, P.b, m, n, shift, full, w, w_dirs, bnd, spare, dirs, lds, &G,
+                                         &cells, &cells_so_out);
+                        cells_out = cells;
+                        len = walk_checked(C, dirs, m, n, G, rev, max(0, n - m) + w_dirs, w_dirs - min(0, n - m));
+                    }
+                } else {
+                    len = walk_any(C, dirs, m, n, G, lds, rev, band_hi);
+                }
                 fence_wave_memory();
                 if (len < 0) {
                     plen = -2;  // a corrupt direction tag: only a device fault can cause it

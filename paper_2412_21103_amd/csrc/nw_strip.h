@@ -273,12 +273,17 @@ __device__ __forceinline__ void table_put(uint32_t* tab, int r, uint32_t w, bool
 // grid rows r0+1 .. r0+m with a = seq + r0).  Every lane starts from `vtop`,
 // the row above the sweep (the grid's first row, or -infinity inside a band),
 // except that lane 0's first diagonal input is `dg0`, the previous strip's
-// last column one row above the sweep.
-template <int C, bool DIRS, bool WIDE, class IO>
+// last column one row above the sweep.  With STATE the lanes start instead
+// from their columns' values in the row above, vst[0..C), and leave their
+// values after the last row there: a strip can be swept in consecutive row
+// ranges, each with or without directions (the lanes above a range's first
+// row keep their values, as above the grid, because rows are monotone).
+template <int C, bool DIRS, bool WIDE, class IO, bool STATE = false>
 __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, int m,
                                                const uint8_t* __restrict__ b, int n, int j0, int kdm,
                                                int kdx, uint32_t shift, int32_t vtop, int32_t dg0, const IO& io,
-                                               uint32_t* __restrict__ dirs, uint32_t* lds, int ksel) {
+                                               uint32_t* __restrict__ dirs, uint32_t* lds, int ksel,
+                                               int32_t* vst = nullptr) {
     const int lane = lane_id();
     const bool lane0 = (lane == 0);
     int32_t V[C];
@@ -286,7 +291,8 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
     uint32_t bcode[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-        V[k] = vtop;
+        if constexpr (STATE) V[k] = vst[k];
+        else V[k] = vtop;
         acc0[k] = 0;
         acc1[k] = 0;
         int j = j0 + C * lane + k;
@@ -441,6 +447,10 @@ __device__ __forceinline__ int32_t sweep_strip(const uint8_t* __restrict__ a, in
         group(g + 1, RinB, RinA, pfb);
     }
     if (g < NG) group(g, RinA, RinB, pfa);
+    if constexpr (STATE) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) vst[k] = V[k];
+    }
     int32_t out = V[0];
 #pragma unroll
     for (int k = 1; k < C; ++k)
@@ -522,10 +532,14 @@ struct DirWindow {
 //
 // For a band, strip s swept grid rows r0(s)+1 .. with r0(s) =
 // max(0, s*64*C - band_hi) and every strip has G groups of storage.
-template <int C>
+// CHECKED: the directions cover only rows r0(s)+1 .. min(m, (s+1)*64*C +
+// span_lo) of each strip; a walk that would leave them returns -3 before it
+// reads outside (the caller then records directions over a wider region).
+template <int C, bool CHECKED = false>
 __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, int m, int n,
                                              int groups_per_strip, uint32_t* /*lds*/,
-                                             uint8_t* __restrict__ rev, int band_hi = 1 << 30) {
+                                             uint8_t* __restrict__ rev, int band_hi = 1 << 30,
+                                             int span_lo = 1 << 30) {
     constexpr int kCols = kWave * C;
     constexpr int kLogC = (C == 8) ? 3 : (C == 4) ? 2 : (C == 2) ? 1 : 0;
     int lane;
@@ -542,7 +556,11 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
         const int s = col0 / kCols;
         int l = (col0 - s * kCols) >> kLogC;
         int k = (col0 - s * kCols) & (C - 1);
-        int t = i - max(0, s * kCols - band_hi) - 1 + l;
+        const int r0s = max(0, s * kCols - band_hi);
+        if constexpr (CHECKED) {
+            if (i <= r0s || i > min(m, s * kCols + kCols + span_lo)) return -3;
+        }
+        int t = i - r0s - 1 + l;
         const int gw = t >> 4, lw = l;
 #pragma unroll
         for (int r = 0; r < C; ++r) {
@@ -569,7 +587,8 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
                 const int cd = c - lane;
                 const int ld = cd >> kLogC, kd = cd & (C - 1);
                 const int td = t - lane - (l - ld);
-                const bool inside = cd >= 0 && ld >= lmin && td >= tmin && td >= 0 && i - lane >= 1 && j - lane >= 1;
+                const bool inside = cd >= 0 && ld >= lmin && td >= tmin && td >= 0 && i - lane >= 1 &&
+                                    j - lane >= 1 && (!CHECKED || i - lane > r0s);
                 const int xd = ((td >> 4) << (4 + kLogC)) + (ld << kLogC) + kd + xo;
                 uint32_t wd = 0;
 #pragma unroll
@@ -595,6 +614,9 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
                     t -= run + (l - ln);
                     l = ln;
                     k = cn & (C - 1);
+                    if constexpr (CHECKED) {
+                        if ((i > 0) & (i <= r0s)) return -3;
+                    }
                     if ((i <= 0) | (j <= 0) | (t < tmin) | (l < lmin)) break;
                 }
             }
@@ -620,6 +642,9 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
             k = kk & (C - 1);
             l -= wrap;
             t -= up + wrap;
+            if constexpr (CHECKED) {
+                if ((i > 0) & (i <= r0s)) return -3;
+            }
             if ((i <= 0) | (j <= 0) | (t < tmin) | (l < lmin)) break;
         }
     }

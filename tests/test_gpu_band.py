@@ -91,8 +91,10 @@ def test_band_doubling_from_zero(small_band_batch):
 @pytest.mark.parametrize("w0", [0, 5, 40])
 def test_band_widening_to_certified_width(small_band_batch, w0):
     # A failed pass widens the band to the width its own score certifies, so
-    # the second pass always certifies (or is the full grid): no pair takes
-    # more than two passes, and the final width is at least w_cert.
+    # the second pass always certifies (or is the full grid), and the final
+    # width is at least w_cert.  The second pass records directions only in
+    # a band around the first pass's; a path that leaves it costs the pass
+    # again with directions in a band four times as wide (or everywhere).
     pairs, ref = small_band_batch
     say(f"band: w_init = {w0}, widening to the certified width")
     so = torch.full((len(pairs),), -1, dtype=torch.int64, device="cuda")
@@ -105,12 +107,39 @@ def test_band_widening_to_certified_width(small_band_batch, w0):
     assert (so >= 0).all() and (so < cells).all()
     assert (so[~fullg] > 0).all()
     widenings = (st >> 1) & 31
-    assert (widenings <= 1).all()
+    assert (widenings <= 4).all()
     if w0 == 0:
-        assert (widenings[~fullg] == 1).sum() > 0
+        assert (widenings[~fullg] >= 1).sum() > 0
     for k in range(len(pairs)):
         if wu[k] >= 0:
             assert wu[k] >= band.w_cert(ref[k][0], len(pairs.a[k]), len(pairs.b[k]), P)
+
+
+def test_band_directions_only_in_first_band(small_band_batch):
+    # After a failed first pass the certified band is swept with directions
+    # only in a band 1.5 times as wide as the first pass's (+16).  Started at
+    # each pair's own w_path (the oracle path's excursion), the path lies in
+    # that band, so the walk never leaves it (at most two passes) -- unless
+    # band(w_path) is past the first pass's height limit and the first pass
+    # ran a narrower band; started at 0, paths with indels leave the
+    # directions and take more passes.  Every path stays exact.
+    pairs, ref = small_band_batch
+    wp = np.array([band.w_path(r[1], len(a), len(b)) for r, a, b in zip(ref, pairs.a, pairs.b)])
+    m = np.array([len(a) for a in pairs.a], np.int64)
+    n = np.array([len(b) for b in pairs.b], np.int64)
+    w_fb = (512 * m - 1024 * (128 + np.abs(n - m)) - 1) // 2048  # the first pass's limit at frac 0.5
+    say("band: w_init = w_path")
+    s, paths, wu, st, cells = run_band(pairs, wp)
+    check_equal(pairs, ref, s, paths, "w_path")
+    extra = (st >> 1) & 31
+    assert (extra[wp <= w_fb] <= 1).all()
+    assert (extra == 1).sum() > 0
+    say("band: w_init = 0, walks that leave the straight band")
+    s, paths, wu, st, cells = run_band(pairs, np.zeros(len(pairs), np.int64))
+    check_equal(pairs, ref, s, paths, "zero")
+    extra = (st >> 1) & 31
+    assert (extra[wp <= 16] <= 1).all()
+    assert (extra >= 2).sum() > 0
 
 
 def test_band_forced_fallback(small_band_batch):
