@@ -48,7 +48,8 @@ struct KArgs {
     // per-step cost of a sweep with C = 2, 4, 8 columns per lane (relative
     // units); the engine picks, per pair and pass, the width whose strips x
     // (rows + ramp) x step cost is smallest
-    int32_t step_cost[3];
+    int32_t step_cost[3];     // per step of the 2-, 4-, 8-column sweeps (this launch's mode)
+    int32_t step_cost_so[3];  // the same without directions (the score-only passes of a banded launch)
     int32_t* scores;
     uint8_t* paths;
     const int64_t* path_off;
@@ -405,8 +406,11 @@ __device__ __forceinline__ int band_height(int C, int m, int n, int w) {
 
 // Sweep width for one pass (the full grid, or band(w)): the C in {2, 4, 8},
 // at least c_min, with the least modelled time, strips x (rows per strip +
-// ramp) x step cost.
-__device__ __forceinline__ int pick_cols(const KArgs& A, int m, int n, bool full, int w, int c_min = 2) {
+// ramp) x step cost.  w_dirs: -2 a pass in the launch's own mode, -1 a
+// score-only pass, >= 0 a pass with directions only in band(w_dirs)'s rows
+// (three row ranges per strip, so two more ramps).
+__device__ __forceinline__ int pick_cols(const KArgs& A, int m, int n, bool full, int w, int c_min = 2,
+                                         int w_dirs = -2) {
     int best = 8;
     int64_t best_cost = INT64_MAX;
 #pragma unroll
@@ -415,7 +419,14 @@ __device__ __forceinline__ int pick_cols(const KArgs& A, int m, int n, bool full
         if (C < c_min) continue;
         const int64_t strips = (n + kWave * C - 1) / (kWave * C);
         const int height = full ? m : band_height(C, m, n, w);
-        const int64_t cost = strips * (int64_t)(height + kWave) * A.step_cost[c];
+        int64_t per_strip;
+        if (w_dirs >= 0) {
+            const int hd = min(height, band_height(C, m, n, w_dirs));
+            per_strip = (int64_t)(hd + kWave) * A.step_cost[c] + (int64_t)(height - hd + 2 * kWave) * A.step_cost_so[c];
+        } else {
+            per_strip = (int64_t)(height + kWave) * (w_dirs == -1 ? A.step_cost_so[c] : A.step_cost[c]);
+        }
+        const int64_t cost = strips * per_strip;
         if (cost < best_cost) {
             best_cost = cost;
             best = C;
@@ -542,14 +553,15 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                     // already does so at fallback_frac of the rows
                     const int64_t lim = (passes > 0 && !A.band_doubling) ? 1024 : A.frac_1024;
                     full = !A.band_ok || w >= mn || (int64_t)(2 * kWave + dlt + 2 * (int64_t)w) * 1024 >= lim * m;
-                    C = uniform(pick_cols(A, m, n, full, w, c_min));
                     const bool score_only = probe && !full;
+                    // the path most likely lies near the failed first pass's
+                    // band: directions in band(1.5 w0 + 16), scores elsewhere
+                    const int wd_next = (DIRS && mixed_next >= 0) ? min(w, mixed_next + mixed_next / 2 + 16) : -2;
+                    C = uniform(pick_cols(A, m, n, full, w, c_min, score_only ? -1 : wd_next));
                     int32_t v;
                     w_dirs = -1;
                     if (DIRS && mixed_next >= 0) {
-                        // the path most likely lies near the failed first pass's
-                        // band: directions in band(1.5 w0 + 16), scores elsewhere
-                        w_dirs = min(w, mixed_next + mixed_next / 2 + 16);
+                        w_dirs = wd_next;
                         mixed_next = -1;
                         v = fill_mixed<WIDE>(C, A, P.a, P.b, m, n, shift, full, w, w_dirs, bnd, spare, dirs, lds, &G,
                                              &cells, &cells_so_out);
@@ -826,8 +838,12 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.kdx_w = KW.kdx;
     A.gap = job.sc.gap;
     step_costs(di.device, job.dirs, A.step_cost);
+    step_costs(di.device, false, A.step_cost_so);
     if (job.force_cols) {
-        for (int c = 0; c < 3; ++c) A.step_cost[c] = ((2 << c) == job.force_cols) ? 1 : kExcluded;
+        for (int c = 0; c < 3; ++c) {
+            A.step_cost[c] = ((2 << c) == job.force_cols) ? 1 : kExcluded;
+            A.step_cost_so[c] = A.step_cost[c];
+        }
     }
     A.scores = job.scores;
     A.paths = job.paths;
