@@ -63,11 +63,29 @@ __global__ __launch_bounds__(256) void k_features(int32_t npairs, const uint8_t*
         const uint8_t* q = pool + (s ? b_off[k] : a_off[k]);
         const int len = s ? n : m;
         const int inc = s ? -1 : 1;
-        // thread t takes the 4-mers starting at 4 consecutive positions
+        // thread t takes the 4-mers starting at 4 consecutive positions; it
+        // reads bytes p .. p+6 as three aligned 32-bit words (a word that
+        // holds at least one byte of the sequence lies within the sequence's
+        // pages) and extracts the 2-bit codes of its bytes; bytes past the end
+        // only reach 4-mers that are not counted
+        const uint32_t* qa = reinterpret_cast<const uint32_t*>((uintptr_t)q & ~(uintptr_t)3);
+        const int sh = (int)((uintptr_t)q & 3);
+        auto word_at = [&](int wi) -> uint32_t {
+            const int first = 4 * wi - sh;  // its first byte, relative to q
+            return (first + 3 >= 0 && first < len) ? qa[wi] : 0u;
+        };
         for (int p = 4 * t; p + 3 < len; p += 4 * 256) {
-            uint32_t w = 0;  // codes of bytes p .. p+6 (as available), 2 bits each
-            const int avail = min(7, len - p);
-            for (int e = 0; e < avail; ++e) w |= (uint32_t)(q[p + e] & 3) << (2 * e);
+            const int b0 = p + sh;
+            const int wi = b0 >> 2;
+            const uint32_t r = (uint32_t)(b0 & 3);
+            const uint32_t w0 = word_at(wi), w1 = word_at(wi + 1), w2 = word_at(wi + 2);
+            const uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, r);  // bytes p .. p+3
+            const uint32_t hi = __builtin_amdgcn_alignbyte(w2, w1, r);  // bytes p+4 .. p+7
+            uint32_t w = 0;  // codes of bytes p .. p+6, 2 bits each
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w |= ((lo >> (8 * e)) & 3u) << (2 * e);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) w |= ((hi >> (8 * e)) & 3u) << (2 * e + 8);
             const int nk = min(4, len - 3 - p);
             for (int e = 0; e < nk; ++e) {
                 const uint32_t c = w >> (2 * e);
