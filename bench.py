@@ -131,9 +131,9 @@ def bench_band_batch(args):
     """The learned-band workload (the metric's configuration): 8192 pairs of
     lengths 1,000..20,000, divergence 1..30%, indel fraction 5..50%, scores and
     paths.  Three arms on the same inputs: (i) full DP, (ii) the certified band
-    with doubling from the best constant starting half-width (chosen on the
-    training pairs by wall time) -- the method without the network -- and
-    (iii) the learned band.  The headline is arm (iii); every arm is compared
+    from the best constant starting half-width (chosen on the training pairs
+    by wall time) -- the method without the network -- and (iii) the learned
+    band, its margin chosen the same way.  The headline is arm (iii); every arm is compared
     with arm (i) on every score and path byte, and arm (iii) with the CPU
     oracle on the cpu_baseline sample."""
     import ctypes
@@ -195,7 +195,7 @@ def bench_band_batch(args):
     vp = ctypes.c_void_p
     ptr = lambda x: vp(x.data_ptr()) if x is not None else vp(0)
     frac = 0.5
-    margin = 0.5       # on the path excursion (widening)
+    margin = 0.5       # on the path excursion (widening); replaced by the best on the training pairs
     margin_cert = 0.1  # on the certified width (doubling)
     ws_bytes = max(nwp.learned_workspace_size(test.n, test.max_len), nwp.batch_workspace_size(test.n, test.max_len))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
@@ -234,6 +234,10 @@ def bench_band_batch(args):
         w0_ms[w0] = min(_events_timed(lambda: const(train, w0), 1, 2, sync, profile=False)[1])
         w0_ms_dbl[w0] = min(_events_timed(lambda: const(train, w0, DBL), 1, 2, sync, profile=False)[1])
     w0_best = min(w0_ms, key=w0_ms.get)
+    # the learned arm's margin, chosen the same way: by wall time on the training pairs
+    mg_ms = {mg: min(_events_timed(lambda: learned(train, mlp, mg), 1, 2, sync, profile=False)[1])
+             for mg in (0.25, 0.5, 1.0, 2.0)}
+    margin = min(mg_ms, key=mg_ms.get)
     w0_best_dbl = min(w0_ms_dbl, key=w0_ms_dbl.get)
 
     def snapshot(B):
@@ -295,6 +299,7 @@ def bench_band_batch(args):
     res_const = arm("const", wall_c, ms_c, prof_c, out_c, "nw_batch_banded")
     res_learned = arm("learned", wall_l, ms_l, prof_l, out_l, "nw_batch_banded")
     res_const["w0"] = w0_best
+    res_learned["margin_search_train_ms"] = {str(k): round(v, 2) for k, v in mg_ms.items()}
     res_const["w0_search_train_ms"] = {str(k): round(v, 2) for k, v in w0_ms.items()}
     res_dbl_const = arm("dbl_const", wall_cd, ms_cd, prof_cd, out_cd, "nw_batch_banded")
     res_dbl_const["w0"] = w0_best_dbl
