@@ -206,3 +206,32 @@ def test_band_empty_and_oversize_pairs():
     assert s2[3] == np.iinfo(np.int32).min and pl[3] == -1
     assert wu2[3] == -1 and st2[3] == 0 and cells2[3] == 0
     assert s2[4] == ref[4][0]
+
+
+@pytest.mark.parametrize("w0", [0, 1, 6])
+def test_band_edge_shapes(w0):
+    # Strip-boundary and ragged shapes through the band passes: the first pass
+    # at a small width fails on mutated pairs, the second records directions
+    # only in a narrow band (its three row ranges per strip empty or not,
+    # depending on the shape and the sweep width), walks that leave it take
+    # wider passes.  Every pair equals the oracle.
+    rng = np.random.default_rng(80 + w0)
+    from workloads import Pairs, mutate, random_seq
+    lens = [1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 700, 1025]
+    A, B = [], []
+    for m in lens:
+        for n in (m, max(1, m - 37), m + 41, max(1, m // 3)):
+            a = random_seq(rng, m)
+            b = mutate(rng, a, 0.2)[:n]
+            if len(b) < n:
+                b = np.concatenate([b, random_seq(rng, n - len(b))])
+            A.append(a)
+            B.append(b)
+    pairs = Pairs(A, B, "band_shapes")
+    ref = [oracle.align(a, b, P) for a, b in zip(A, B)]
+    say(f"band: {len(A)} edge shapes from w0 = {w0}")
+    s, paths, wu, st, cells = run_band(pairs, None, w_default=w0)
+    check_equal(pairs, ref, s, paths, f"shapes w0={w0}")
+    s, paths, wu, st, cells = run_band(pairs, None, w_default=w0, scoring=(2, -3, -2))
+    ref2 = [oracle.align(a, b, (2, -3, -2)) for a, b in zip(A, B)]
+    check_equal(pairs, ref2, s, paths, f"shapes w0={w0} other scoring")
