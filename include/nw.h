@@ -233,9 +233,15 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  * region contains this one, so its score is at least S_R and the second pass
  * always certifies.  Because the first pass serves mostly to find S_R, it
  * runs score-only (no directions); if it certifies after all, the same band
- * is swept again with directions.  With the flag NW_BAND_DOUBLING, w doubles
- * instead (0 becomes 1), every pass records directions, and a pair may take
- * more passes.  The full
+ * is swept again with directions.  The widened pass records directions only
+ * in the rows of band(1.5 w + 16) (w the first pass's width), where the path
+ * most likely runs, and sweeps the rest of its band score-only; the
+ * traceback checks that it stays in those rows, and if it would leave them
+ * the pass is swept again with directions in a band four times as wide (+64),
+ * or everywhere once that covers the certified band.  The traceback never
+ * reads a direction that was not recorded, so results do not depend on w.
+ * With the flag NW_BAND_DOUBLING, w doubles instead (0 becomes 1), every
+ * pass records directions, and a pair may take more passes.  The full
  * grid is used directly once w >= min(m,n), when 2*gap >= c_d, or once the
  * band's height 128 + |D| + 2w reaches fallback_frac of m -- for a first pass
  * or any doubled one; a widened pass, which is certain to certify, takes the
@@ -252,7 +258,8 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  * passes after the first, bit 6 full grid, bit 7 certificate not applicable;
  * cells[k] =
  * cells swept over all passes; cells_score_only[k] = those of them swept
- * score-only (the first pass's, when it ran without directions).  A pair with m == 0 or n == 0 reports
+ * score-only (the first pass's, when it ran without directions, and the
+ * rows of later passes that recorded none).  A pair with m == 0 or n == 0 reports
  * w_used -1, the full-grid bit and 0 cells; a pair over max_len reports
  * w_used -1, status 0 and 0 cells.
  * ------------------------------------------------------------------------ */
