@@ -551,6 +551,35 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
 #pragma unroll
     for (int r = 0; r < C; ++r) win[r] = 0;
     uint32_t buf = 0;
+    // the lookahead tree: lane 1 + d after move d + 1 (1 L, 2 U, 3 D), lane
+    // 4 + 3*d0 + d1 after two, lane 13 + 9*d0 + 3*d1 + d2 after three (digits
+    // d = tag - 1); la, lb: rows and columns the lane's moves take
+    int lvl = 4, la = 0, lb = 0;
+    {
+        int dg[3] = {-1, -1, -1};
+        if (lane == 0) {
+            lvl = 0;
+        } else if (lane < 4) {
+            lvl = 1;
+            dg[0] = lane - 1;
+        } else if (lane < 13) {
+            lvl = 2;
+            dg[0] = (lane - 4) / 3;
+            dg[1] = (lane - 4) % 3;
+        } else if (lane < 40) {
+            lvl = 3;
+            dg[0] = (lane - 13) / 9;
+            dg[1] = ((lane - 13) / 3) % 3;
+            dg[2] = (lane - 13) % 3;
+        }
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            if (dg[e] >= 0) {
+                la += (dg[e] + 1) >> 1;
+                lb += (dg[e] + 1) & 1;
+            }
+        }
+    }
     while (i > 0 && j > 0) {
         const int col0 = j - 1;
         const int s = col0 / kCols;
@@ -572,8 +601,6 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
         }
         const int tmin = 16 * (gw - 3), lmin = max(lw - 15, 0);
         const int xo = ((3 - gw) << (4 + kLogC)) + ((15 - lw) << kLogC);
-        int cur_r = -1;
-        uint32_t cur = 0;
         bool diag = true;
         for (;;) {
             if (diag) {
@@ -620,28 +647,55 @@ __device__ __forceinline__ int64_t walk_back(const uint32_t* __restrict__ dirs, 
                     if ((i <= 0) | (j <= 0) | (t < tmin) | (l < lmin)) break;
                 }
             }
-            const int x = ((t >> 4) << (4 + kLogC)) + (l << kLogC) + k + xo;
-            if ((x >> 6) != cur_r) {
-                cur_r = x >> 6;
-                cur = win[0];
+            // Lookahead round: lane 0 holds the current cell, lanes 1..39 the
+            // cells one, two and three moves on along every possible move
+            // sequence (la, lb: the rows and columns the lane's moves take).
+            // Each lane reads its cell's tag from the window (ds_bpermute);
+            // four dependent v_readlanes then follow the actual path for up
+            // to four moves, stopping at a cell outside the window.
+            const int c = (l << kLogC) + k;
+            const int cd = c - lb;
+            const int ld = cd >> kLogC, kd = cd & (C - 1);
+            const int td = t - la - (l - ld);
+            const bool ok = lvl < 4 && cd >= 0 && ld >= lmin && td >= tmin && td >= 0 && i - la >= 1 &&
+                            j - lb >= 1 && (!CHECKED || i - la > r0s);
+            const int xd = ((td >> 4) << (4 + kLogC)) + (ld << kLogC) + kd + xo;
+            uint32_t wd = 0;
 #pragma unroll
-                for (int r = 1; r < C; ++r) cur = (cur_r == r) ? win[r] : cur;
+            for (int r = 0; r < C; ++r) {
+                const uint32_t v = (uint32_t)__builtin_amdgcn_ds_bpermute((xd & 63) << 2, (int)win[r]);
+                wd = ((xd >> 6) == r) ? v : wd;
             }
-            const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)cur, x & 63);
-            const int tag = (int)((word >> (2 * (t & 15))) & 3u);
-            if (__builtin_expect(tag == 0, 0)) return -1;
-            buf = (lane == (int)(q & 63)) ? (uint32_t)(4 - tag) : buf;
-            ++q;
-            if (__builtin_expect((q & 63) == 0, 0)) rev[q - 64 + lane] = (uint8_t)buf;
-            const int up = tag >> 1, left = tag & 1;
-            diag = tag == 3;
-            const int kk = k - left;
-            const int wrap = (int)((uint32_t)kk >> 31);
-            i -= up;
-            j -= left;
-            k = kk & (C - 1);
-            l -= wrap;
-            t -= up + wrap;
+            const int tg = ok ? (int)((wd >> (2 * (td & 15))) & 3u) : 0;
+            const int t0 = __builtin_amdgcn_readlane(tg, 0);
+            if (__builtin_expect(t0 == 0, 0)) return -1;  // the current cell is always in the window
+            const int t1 = __builtin_amdgcn_readlane(tg, t0);
+            const int t2 = __builtin_amdgcn_readlane(tg, 3 * t0 + t1);
+            const int t3 = __builtin_amdgcn_readlane(tg, 9 * t0 + 3 * t1 + t2);
+            const int nres = (t1 == 0) ? 1 : (t2 == 0) ? 2 : (t3 == 0) ? 3 : 4;
+            const int s1 = nres > 1 ? t1 : 0, s2 = nres > 2 ? t2 : 0, s3 = nres > 3 ? t3 : 0;
+            const int a = (t0 >> 1) + (s1 >> 1) + (s2 >> 1) + (s3 >> 1);
+            const int b = (t0 & 1) + (s1 & 1) + (s2 & 1) + (s3 & 1);
+            {
+                // moves q .. q+nres-1 go to lanes (q+d) % 64, the block flushed
+                // once it fills
+                const int q0 = (int)(q & 63);
+                const int dd = (lane - q0) & 63;
+                const uint32_t mv = (uint32_t)(4 - (dd == 0 ? t0 : dd == 1 ? t1 : dd == 2 ? t2 : t3));
+                const int e1 = min(kWave, q0 + nres);
+                buf = (lane >= q0 && lane < e1) ? mv : buf;
+                if (e1 == kWave) rev[(q & ~(int64_t)63) + lane] = (uint8_t)buf;
+                buf = (lane < q0 + nres - kWave) ? mv : buf;
+                q += nres;
+            }
+            diag = (nres == 1 ? t0 : nres == 2 ? t1 : nres == 3 ? t2 : t3) == 3;
+            i -= a;
+            j -= b;
+            const int cn = c - b;
+            const int ln = cn >> kLogC;
+            t -= a + (l - ln);
+            l = ln;
+            k = cn & (C - 1);
             if constexpr (CHECKED) {
                 if ((i > 0) & (i <= r0s)) return -3;
             }
