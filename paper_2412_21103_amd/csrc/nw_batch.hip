@@ -30,6 +30,7 @@ struct KArgs {
     const int32_t* w_init;  // per pair initial half-width, or null
     int32_t w_default;
     int32_t frac_1024;      // fall back to the full grid once the band is this fraction of m (x1024)
+    int32_t prio_jobs;      // the first prio_jobs jobs of the order run at raised wave priority
     int32_t cd;             // max(match, mismatch)
     int32_t band_ok;        // the certificate applies (2 gap < cd)
     int32_t band_doubling;  // widen a failed band by doubling (else to its certified width)
@@ -485,6 +486,10 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
     for (;;) {
         const int p = part_lo + uniform(atomicAdd(WIDE ? A.queue2 : A.queue, lane == 0 ? 1 : 0));
         if (p >= part_hi) break;
+        // the largest jobs (the front of the order) set the makespan: their
+        // waves win the issue arbitration against the SIMD's other waves
+        if ((p - part_lo) < A.prio_jobs) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(0);
         const int job = uniform(A.order[p]);
         const Pair P = get_pair<ALLPAIRS>(A, job);
         const int m = uniform(P.m), n = uniform(P.n);
@@ -854,6 +859,12 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.w_init = job.w_init;
     A.w_default = job.w_default;
     A.frac_1024 = job.frac_1024;
+    // the first round of jobs (one per wave) runs at raised priority: once a
+    // wave moves on to a later, smaller job, the SIMD's arbitration favours
+    // the wave still on its large first job, which shortens the tail
+    // (measured: 4096-pair batch 1.70 -> 1.56 ms, full DP of the 8192-pair
+    // workload 190 -> 174 ms, a quarter or half of the waves less)
+    A.prio_jobs = (int32_t)std::min<int64_t>(job.njobs, L.grid * kWavesPerBlock);
     A.cd = std::max(job.sc.match, job.sc.mismatch);
     A.band_ok = 2 * job.sc.gap < A.cd ? 1 : 0;
     A.band_doubling = job.band_doubling ? 1 : 0;
