@@ -89,6 +89,7 @@ struct CoArgs {
     int64_t off_tie;   // within a slot
     int64_t off_walk;  // within a slot
     int32_t spin;      // polls before a team wait gives up
+    int32_t prio_jobs; // the first prio_jobs single-wave jobs run at raised wave priority
     uint32_t* fault;   // host-visible device-fault word (may be null)
     uint32_t* masks;   // byte-presence masks: a of pair p at 16p, b at 16p+8
 };
@@ -528,6 +529,10 @@ __global__ __launch_bounds__(kWave * kCoWaves, co_blocks_per_cu(ENUM)) void k_co
     for (;;) {
         const int job = first + uniform(atomicAdd(A.next_job, lane == 0 ? 1 : 0));
         if (job >= A.npairs) break;
+        // the first round (the largest single-wave jobs) wins the SIMD's issue
+        // arbitration against waves already on later, smaller jobs
+        if (job - first < A.prio_jobs) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(0);
         const int p = uniform(A.order[job]);
         const int32_t m = uniform(A.a_len[p]), n = uniform(A.b_len[p]);
         const bool ok = m >= 0 && n >= 0 && m <= A.max_len && n <= A.max_len;
@@ -680,6 +685,7 @@ int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, 
     A.off_walk = L.off_walk;
     A.spin = di.spin_limit;
     A.fault = di.fault;
+    A.prio_jobs = (int32_t)std::min<int64_t>(npairs, slots);
     const unsigned pg = (unsigned)((npairs + 255) / 256);
     hipLaunchKernelGGL(k_co_zero, dim3((kCoHeaderInts + 255) / 256), dim3(256), 0, st, A.hist, kCoHeaderInts);
     hipLaunchKernelGGL(k_co_alpha, dim3((unsigned)((2 * (int64_t)npairs + 3) / 4)), dim3(256), 0, st, A);
