@@ -289,10 +289,12 @@ def bench_band_batch(args):
                       "certified_first_pass": round(float(np.mean(st & 1)), 4),
                       "extra_passes_mean": round(float(np.mean((st >> 1) & 31)), 3),
                       "full_grid_frac": round(float(np.mean((st & 0x40) != 0)), 4)})
-        k = prof.get(kernel)
+        k = kernel_ms(prof, kernel)
         if k:
             d["kernel"] = kernel
-            d["kernel_ms"] = round(k[1] / k[0], 4)
+            d["kernel_ms"] = round(k, 4)
+            if kernel == "nw_batch_banded" and prof.get(PROBE_KERNEL):
+                d["probe_kernel_ms"] = round(kernel_ms(prof, PROBE_KERNEL), 4)
         return d
 
     res_full = arm("full", wall_f, ms_f, prof_f, None, "nw_batch")
@@ -311,19 +313,19 @@ def bench_band_batch(args):
     # with directions at FILL_OPS_PER_CELL, those of score-only passes at
     # SCORE_OPS_PER_CELL (and again at the 7 and 5 operations per cell the
     # scope counts name)
-    kb = prof_l.get("nw_batch_banded")
+    kb_ms = kernel_ms(prof_l, "nw_batch_banded")
     swept_cells = float(out_l[5].sum())
     so_cells = float(out_l[6].sum())
     dir_cells = swept_cells - so_cells
     ops = FILL_OPS_PER_CELL * dir_cells + SCORE_OPS_PER_CELL * so_cells
-    roof = alu_roofline("nw_batch_banded", ops, kb[1] / kb[0] if kb else None, 1)
+    roof = alu_roofline(BAND_KERNEL_LABEL, ops, kb_ms, 1)
     if roof:
         roof.pop("ops_per_cell")
         roof.update({"cells_with_directions": dir_cells, "cells_score_only": so_cells,
                      "ops_per_cell": {"with_directions": FILL_OPS_PER_CELL, "score_only": SCORE_OPS_PER_CELL}})
         roof["traffic"] = traffic_record(BAND_COUNTERS, BAND_SOURCES)
         ops_scope = 7 * dir_cells + 5 * so_cells
-        roof["frac_at_scope_counts"] = round(ops_scope / (kb[1] / kb[0] * 1e-3) / 1e12 / PEAK_INT32_TOPS, 4)
+        roof["frac_at_scope_counts"] = round(ops_scope / (kb_ms * 1e-3) / 1e12 / PEAK_INT32_TOPS, 4)
         roof["valu"] = valu_record(BAND_VALU, BAND_SOURCES)
 
     cpu = exact_oracle = None
@@ -387,6 +389,25 @@ def common_fields(args, value, ms_per_step, config, roofline, cpu, metric_suffix
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+
+
+# The banded launch with paths runs its score-only first passes in a launch of
+# their own first; the banded kernel's time is the two together.
+PROBE_KERNEL = "nw_batch_banded_probe"
+BAND_KERNEL_LABEL = "nw_batch_banded (+ nw_batch_banded_probe)"
+
+
+def kernel_ms(prof, kernel):
+    """Mean per-call time of `kernel` (HIP events around each launch); for the
+    banded kernel with paths, plus its probe launch's."""
+    k = prof.get(kernel)
+    if not k:
+        return None
+    ms = k[1] / k[0]
+    if kernel == "nw_batch_banded" and prof.get(PROBE_KERNEL):
+        p = prof[PROBE_KERNEL]
+        ms += p[1] / p[0]
+    return ms
 
 
 def alu_roofline(kernel, cells, kernel_ms, ops_per_cell):

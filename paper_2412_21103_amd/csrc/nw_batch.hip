@@ -72,6 +72,12 @@ struct KArgs {
     uint8_t* rev;
     int64_t rev_stride;
     uint32_t* fault;  // host-visible device-fault word (may be null)
+    // A banded launch with paths whose score-only first passes ran before it,
+    // in their own launch (k_probe, phase 1): per job, that pass's score and
+    // cells; phase 2 is the launch that continues from them.
+    int32_t* probe_score;
+    int64_t* probe_cells;
+    int32_t probe_phase;
 };
 
 struct Pair {
@@ -116,6 +122,75 @@ __device__ __forceinline__ Pair get_pair(const KArgs& A, int job) {
         p.n = A.b_len[job];
     }
     return p;
+}
+
+// ---- the certified band's schedule of widths ----
+
+struct BandPlan {
+    int w0;       // the first pass's half-width
+    int mn;       // min(m, n)
+    int64_t dlt;  // |n - m|
+};
+
+// The first width: the pair's proposal (or the launch default).  The
+// fallback test uses the narrowest sweep's band height: full grid once
+// 128 + |D| + 2w >= frac * m.  A first width beyond that is first tried at
+// the widest band below it, so only a failed band sends a pair to the full
+// grid.
+__device__ __forceinline__ BandPlan band_plan(const KArgs& A, int job, int m, int n) {
+    BandPlan b;
+    b.w0 = max(0, A.w_init ? A.w_init[job] : A.w_default);
+    b.mn = min(m, n);
+    b.dlt = n > m ? n - m : m - n;
+    const int64_t fb_num = (int64_t)A.frac_1024 * m - 1024 * (2 * kWave + b.dlt) - 1;
+    const int64_t w_fb = fb_num >= 0 ? fb_num / 2048 : -1;
+    if (b.w0 < b.mn && w_fb >= 0 && b.w0 > w_fb) b.w0 = (int)w_fb;
+    return b;
+}
+
+// Whether pass number `passes` (0 = the first) at half-width w takes the
+// full grid.  A pass after a failed one is certain to certify (unless
+// doubling), so it takes the full grid only once the band covers every row
+// of a strip; a first pass, which may fail, already does so at fallback_frac
+// of the rows.
+__device__ __forceinline__ bool band_full(const KArgs& A, int m, const BandPlan& b, int w, int passes) {
+    const int64_t lim = (passes > 0 && !A.band_doubling) ? 1024 : A.frac_1024;
+    return !A.band_ok || w >= b.mn || (int64_t)(2 * kWave + b.dlt + 2 * (int64_t)w) * 1024 >= lim * m;
+}
+
+// The best score a path that leaves band(w) can reach (U_out).
+__device__ __forceinline__ int64_t band_u_out(const KArgs& A, const BandPlan& b, int w) {
+    return (int64_t)A.cd * (b.mn - w - 1) + (int64_t)A.gap * (b.dlt + 2 * (int64_t)w + 2);
+}
+
+// The width a failed band's score certifies.  The failed score S_R <=
+// U_out(w).  U_out falls by cd - 2 gap per unit of w, so the smallest w'
+// with S_R > U_out(w') is num / (cd - 2 gap) + 1 > w.  The next region
+// contains this one (it is wider, and its sweep width is no narrower, so its
+// strips' row ranges cover these), so its score is at least S_R and the next
+// pass certifies.
+__device__ __forceinline__ int band_widen(const KArgs& A, const BandPlan& b, int w, int32_t score) {
+    const int64_t num = (int64_t)A.cd * (b.mn - 1) + (int64_t)A.gap * (b.dlt + 2) - score;
+    const int64_t den = (int64_t)A.cd - 2 * (int64_t)A.gap;
+    return (int)min((int64_t)b.mn, max((int64_t)w + 1, num / den + 1));
+}
+
+// Cost of job q in a banded launch that continues from its probe (phase
+// 2): the cells of the passes still to come, those with directions counted
+// twice.  A first pass that certified is swept again with directions; one
+// that failed widens to the width its score certifies, with directions in
+// band(1.5 w0 + 16); a first pass on the full grid stays there.
+__device__ __forceinline__ int64_t band_job_cost(const KArgs& A, int q, int m, int n) {
+    const int64_t mn64 = (int64_t)m * n;
+    if (m <= 0 || n <= 0 || m > A.max_len || n > A.max_len) return mn64;
+    const BandPlan bp = band_plan(A, q, m, n);
+    if (band_full(A, m, bp, bp.w0, 0)) return 2 * mn64;
+    auto area = [&](int w) { return (int64_t)n * min((int64_t)m, (int64_t)kWave * 8 + bp.dlt + 2 * (int64_t)w); };
+    const int32_t s = A.probe_score[q];
+    if ((int64_t)s > band_u_out(A, bp, bp.w0)) return 2 * area(bp.w0);
+    const int w1 = band_widen(A, bp, bp.w0, s);
+    if (band_full(A, m, bp, w1, 1)) return 2 * mn64;
+    return area(w1) + area(min(w1, bp.w0 + bp.w0 / 2 + 16));
 }
 
 // ---- planning kernels: zero the counters, bucket jobs by cost, scatter ----
@@ -166,7 +241,11 @@ __device__ __forceinline__ int job_bucket(const KArgs& A, int q) {
         mask_index<ALLPAIRS>(p, q, &qa, &qb);
         wide = code_shift(A.masks + qa * 8, A.masks + qb * 8) < 0;
     }
-    return cost_bucket((int64_t)p.m * p.n) + (wide ? kBuckets : 0);
+    int64_t cost = (int64_t)p.m * p.n;
+    if constexpr (!ALLPAIRS) {
+        if (A.probe_phase == 2) cost = band_job_cost(A, q, p.m, p.n);
+    }
+    return cost_bucket(cost) + (wide ? kBuckets : 0);
 }
 
 template <bool ALLPAIRS>
@@ -533,16 +612,8 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                 // beat the best score any path leaving band(w) can reach, widen the
                 // band to the width that this score itself certifies, or take the
                 // full grid once the band is so wide that it is cheaper
-                w = max(0, A.w_init ? A.w_init[job] : A.w_default);
-                const int mn = min(m, n);
-                const int64_t dlt = n > m ? n - m : m - n;
-                // the fallback test uses the narrowest sweep's band height:
-                // full grid once 128 + |D| + 2w >= frac * m.  A first width
-                // beyond that is first tried at the widest band below it, so
-                // only a failed band sends a pair to the full grid.
-                const int64_t fb_num = (int64_t)A.frac_1024 * m - 1024 * (2 * kWave + dlt) - 1;
-                const int64_t w_fb = fb_num >= 0 ? fb_num / 2048 : -1;
-                if (w < mn && w_fb >= 0 && w > w_fb) w = (int)w_fb;
+                const BandPlan bp = band_plan(A, job, m, n);
+                w = bp.w0;
                 int c_min = 2;
                 // With widening, a first pass that does not certify serves only to
                 // find the region's score, so it runs score-only (no direction
@@ -552,12 +623,7 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                 bool certified_first = false;
                 int mixed_next = -1;  // after a failed first pass: record directions only in its band
                 for (;;) {
-                    // a pass after a failed one is certain to certify (unless
-                    // doubling), so it takes the full grid only once the band
-                    // covers every row of a strip; a first pass, which may fail,
-                    // already does so at fallback_frac of the rows
-                    const int64_t lim = (passes > 0 && !A.band_doubling) ? 1024 : A.frac_1024;
-                    full = !A.band_ok || w >= mn || (int64_t)(2 * kWave + dlt + 2 * (int64_t)w) * 1024 >= lim * m;
+                    full = band_full(A, m, bp, w, passes);
                     const bool score_only = probe && !full;
                     // the path most likely lies near the failed first pass's
                     // band: directions in band(1.5 w0 + 16), scores elsewhere
@@ -571,6 +637,11 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                         v = fill_mixed<WIDE>(C, A, P.a, P.b, m, n, shift, full, w, w_dirs, bnd, spare, dirs, lds, &G,
                                              &cells, &cells_so_out);
                         score = v + A.gap * (m + n);
+                    } else if (score_only && A.probe_phase == 2) {
+                        // this pass ran in the probe launch (k_probe)
+                        score = A.probe_score[job];
+                        cells += A.probe_cells[job];
+                        cells_so_out += A.probe_cells[job];
                     } else if (score_only) {
                         const int64_t before = cells;
                         v = fill_any<false, WIDE>(C, A, P.a, P.b, m, n, shift, false, w, bnd, spare, nullptr, lds, &G,
@@ -585,8 +656,7 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                     ++passes;
                     probe = false;
                     if (full) break;
-                    const int64_t u_out = (int64_t)A.cd * (mn - w - 1) + (int64_t)A.gap * (dlt + 2 * (int64_t)w + 2);
-                    if ((int64_t)score > u_out) {
+                    if ((int64_t)score > band_u_out(A, bp, w)) {
                         if (passes == 1) certified_first = true;
                         if (!score_only) break;
                         c_min = C;  // the same band again, with directions
@@ -596,17 +666,9 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
                         w = max(1, 2 * w);
                         continue;
                     }
-                    // The failed score S_R <= U_out(w).  U_out falls by cd - 2 gap
-                    // per unit of w, so the smallest w' with S_R > U_out(w') is
-                    // num / (cd - 2 gap) + 1 > w.  The next region contains this
-                    // one (it is wider, and its sweep width is no narrower, so
-                    // its strips' row ranges cover these), so its score is at
-                    // least S_R and the next pass certifies.
-                    const int64_t num = (int64_t)A.cd * (mn - 1) + (int64_t)A.gap * (dlt + 2) - score;
-                    const int64_t den = (int64_t)A.cd - 2 * (int64_t)A.gap;
                     if (score_only) mixed_next = w;
                     w_dirs = -1;
-                    w = (int)min((int64_t)mn, max((int64_t)w + 1, num / den + 1));
+                    w = band_widen(A, bp, w, score);
                     c_min = C;
                 }
                 w_out = full ? -1 : w;
@@ -679,6 +741,53 @@ __global__ __launch_bounds__(kBlockThreads, blocks_per_cu(DIRS)) void k_batch(KA
     }
 }
 
+// The score-only first passes of a banded launch with paths, on their own:
+// each pair whose first pass is score-only (widening, not the full grid)
+// sweeps band(w0) without directions and leaves the region's score and the
+// cells swept in probe_score / probe_cells, which the launch with paths
+// (phase 2) takes in place of that pass.  Same order, sweep width and result
+// as that pass in k_batch; run at the score-only occupancy, 4 waves per SIMD
+// instead of 2.  Each wave's boundary slot lies in the direction-word area,
+// which this launch does not otherwise use (the host checks it fits).
+template <bool WIDE>
+__global__ __launch_bounds__(kBlockThreads, blocks_per_cu(false)) void k_probe(KArgs A) {
+    __shared__ uint32_t smem[kWavesPerBlock][StripShape<8>::kLdsWords];
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    uint32_t* lds = smem[wave];
+    const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    int32_t* bnd = A.bnd + slot * A.bnd_stride;
+    int32_t* spare = bnd + A.bnd_stride - 1;
+    // every lane runs every path of the job loop (as in k_batch)
+    const int part_lo = WIDE ? uniform(*A.n_narrow) : 0;
+    const int part_hi = WIDE ? A.njobs : uniform(*A.n_narrow);
+    for (;;) {
+        const int p = part_lo + uniform(atomicAdd(WIDE ? A.queue2 : A.queue, lane == 0 ? 1 : 0));
+        if (p >= part_hi) break;
+        if ((p - part_lo) < A.prio_jobs) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(0);
+        const int job = uniform(A.order[p]);
+        const Pair P = get_pair<false>(A, job);
+        const int m = uniform(P.m), n = uniform(P.n);
+        if (m > A.max_len || n > A.max_len || m <= 0 || n <= 0) continue;
+        const BandPlan bp = band_plan(A, job, m, n);
+        if (band_full(A, m, bp, bp.w0, 0)) continue;
+        uint32_t shift = 0;
+        if (!WIDE) {
+            int64_t qa, qb;
+            mask_index<false>(P, job, &qa, &qb);
+            shift = (uint32_t)max(0, uniform(code_shift(A.masks + qa * 8, A.masks + qb * 8)));
+        }
+        const int C = uniform(pick_cols(A, m, n, false, bp.w0, 2, -1));
+        int G = 0;
+        int64_t cells = 0;
+        const int32_t v =
+            fill_any<false, WIDE>(C, A, P.a, P.b, m, n, shift, false, bp.w0, bnd, spare, nullptr, lds, &G, &cells);
+        A.probe_score[job] = v + A.gap * (m + n);
+        A.probe_cells[job] = cells;
+    }
+}
+
 // ---- host side ----
 
 // Relative per-step cost of the 2-, 4- and 8-column sweeps.  Defaults:
@@ -739,7 +848,7 @@ constexpr int kMaxCols = 8;  // slots are sized for the widest sweep, which boun
 
 struct Layout {
     int64_t nslots, grid;
-    size_t off_order, off_masks, off_bnd, off_dirs, off_rev, total;
+    size_t off_order, off_masks, off_probe_score, off_probe_cells, off_bnd, off_dirs, off_rev, total;
     int64_t bnd_stride, dirs_stride, rev_stride;
 };
 
@@ -772,7 +881,10 @@ static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const Device
     // masks: eight words for each of the 2 njobs sequences (pairs), which also
     // covers the nseq <= njobs sequences of all-pairs
     const size_t mask_bytes = align_up((size_t)std::max(njobs, 1) * 2 * 32, 256);
-    const size_t fixed = align_up(kHeaderBytes + (size_t)std::max(njobs, 1) * 4, 256) + mask_bytes + 3 * 256;
+    // the probe launch's records: a score (4 B) and a cell count (8 B) per job
+    const size_t probe_bytes = align_up((size_t)std::max(njobs, 1) * 4, 256) + align_up((size_t)std::max(njobs, 1) * 8, 256);
+    const size_t fixed =
+        align_up(kHeaderBytes + (size_t)std::max(njobs, 1) * 4, 256) + mask_bytes + probe_bytes + 3 * 256;
     const int64_t want = ((int64_t)njobs + kWavesPerBlock - 1) / kWavesPerBlock;
     int64_t grid = std::min<int64_t>(std::max<int64_t>(want, 1), (int64_t)di.cus * blocks_per_cu(dirs));
     const size_t budget = std::min(ws_limit, fixed + std::max(kSlotBudget, per_block));
@@ -789,6 +901,10 @@ static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const Device
     off = align_up(off + (size_t)std::max(njobs, 1) * 4, 256);
     L.off_masks = off;
     off += mask_bytes;
+    L.off_probe_score = off;
+    off += align_up((size_t)std::max(njobs, 1) * 4, 256);
+    L.off_probe_cells = off;
+    off += align_up((size_t)std::max(njobs, 1) * 8, 256);
     L.off_bnd = off;
     off = align_up(off + (size_t)L.nslots * L.bnd_stride * 4, 256);
     L.off_dirs = off;
@@ -819,6 +935,38 @@ static void launch_engine(const KArgs& A, int64_t grid, hipStream_t st) {
     ProfScope ps("nw_batch_wide", st);
     hipLaunchKernelGGL((k_batch<DIRS, ALLPAIRS, BANDED, true>), dim3((unsigned)grid), dim3(kBlockThreads), 0, st,
                        A);
+}
+
+// The score-only first passes of a banded launch with paths (k_probe), then
+// the order again for the launch with paths, which continues from the
+// records (*A becomes phase 2).  The probe waves' boundary slots go in the
+// direction-word area, as many as fit.
+static void launch_probe(KArgs& A, const Layout& L, const DeviceInfo& di, int32_t njobs, hipStream_t st) {
+    const size_t per_block = (size_t)kWavesPerBlock * (size_t)L.bnd_stride * 4;
+    const int64_t want = ((int64_t)njobs + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t room = (int64_t)((L.off_rev - L.off_dirs) / per_block);
+    const int64_t grid = std::min<int64_t>(std::min<int64_t>(want, (int64_t)di.cus * blocks_per_cu(false)), room);
+    if (grid < 1) return;  // no room: k_batch sweeps the first passes itself
+    A.probe_phase = 2;
+    KArgs P = A;
+    P.probe_phase = 1;
+    P.bnd = (int32_t*)A.dirs;
+    P.prio_jobs = (int32_t)std::min<int64_t>(njobs, grid * kWavesPerBlock);
+    {
+        ProfScope ps("nw_batch_banded_probe", st);
+        hipLaunchKernelGGL(k_probe<false>, dim3((unsigned)grid), dim3(kBlockThreads), 0, st, P);
+    }
+    {
+        ProfScope ps("nw_batch_wide", st);
+        hipLaunchKernelGGL(k_probe<true>, dim3((unsigned)grid), dim3(kBlockThreads), 0, st, P);
+    }
+    // a new largest-first order by the cost of what is left of each job
+    constexpr int kHeaderInts = (int)(kHeaderBytes / 4);
+    const unsigned pb = (unsigned)((njobs + 255) / 256);
+    hipLaunchKernelGGL(k_zero, dim3((kHeaderInts + 255) / 256), dim3(256), 0, st, A.queue, kHeaderInts);
+    hipLaunchKernelGGL(k_hist<false>, dim3(pb), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor, A.n_narrow);
+    hipLaunchKernelGGL(k_scatter<false>, dim3(pb), dim3(256), 0, st, A);
 }
 
 int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st, const DeviceInfo& di) {
@@ -872,6 +1020,9 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.status = job.status;
     A.cells = job.cells;
     A.cells_so = job.cells_so;
+    A.probe_phase = 0;
+    A.probe_score = (int32_t*)(base + L.off_probe_score);
+    A.probe_cells = (int64_t*)(base + L.off_probe_cells);
     A.queue = (int32_t*)base;
     A.queue2 = (int32_t*)(base + 4);
     A.n_narrow = (int32_t*)(base + 8);
@@ -903,6 +1054,7 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor, A.n_narrow);
         hipLaunchKernelGGL(k_scatter<false>, dim3(pb), dim3(256), 0, st, A);
         if (job.banded) {
+            if (job.dirs && !job.band_doubling) launch_probe(A, L, di, job.njobs, st);
             if (job.dirs) launch_engine<true, false, true>(A, L.grid, st);
             else launch_engine<false, false, true>(A, L.grid, st);
         } else {

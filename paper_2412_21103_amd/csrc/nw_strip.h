@@ -254,8 +254,15 @@ __device__ __forceinline__ typename IO::Slot wait_slot(const IO& io, int r, bool
 template <bool WIDE>
 __device__ __forceinline__ uint32_t table_word(int r, int m, uint32_t x, int kdm, int kdx, uint32_t shift) {
     const bool valid = (r >= 1 && r <= m);
-    if constexpr (WIDE) return wide_word(valid, x, kdx);
-    else return valid ? row_word(sym_code(x, shift), kdm, kdx) : kSentinelWord;
+    if constexpr (WIDE) {
+        return wide_word(valid, x, kdx);
+    } else {
+        // the word is computed for every lane and then selected: written as
+        // one conditional expression it became a branch inside the sweep loop
+        // in some builds, and the kernel's registers then spilled
+        const uint32_t w = row_word(sym_code(x, shift), kdm, kdx);
+        return valid ? w : kSentinelWord;
+    }
 }
 
 // Write row r's word to the table (index r & 255, and its mirror copy when the
