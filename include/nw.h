@@ -233,7 +233,11 @@ int nw_align_batch(int32_t npairs, const uint8_t *pool, const int64_t *a_off,
  * region contains this one, so its score is at least S_R and the second pass
  * always certifies.  Because the first pass serves mostly to find S_R, it
  * runs score-only (no directions); if it certifies after all, the same band
- * is swept again with directions.  The widened pass records directions only
+ * is swept again with directions.  With paths requested, the call runs every
+ * pair's score-only first pass in a launch of its own before the others,
+ * then orders the pairs again by the cost of their remaining passes; the
+ * results are the same as if each pair ran its passes in one go.  The
+ * widened pass records directions only
  * in the rows of band(1.5 w + 16) (w the first pass's width), where the path
  * most likely runs, and sweeps the rest of its band score-only; the
  * traceback checks that it stays in those rows, and if it would leave them
