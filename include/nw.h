@@ -137,6 +137,11 @@ int nw_set_walk_limit(int64_t moves);
 /* Banded and learned batch calls: widen a failed band by doubling it rather
  * than to the width its score certifies (see nw_align_batch_banded). */
 #define NW_BAND_DOUBLING 0x4u
+/* Banded and learned batch calls with paths: run every pass of a pair in one
+ * launch, without the separate launch of the score-only first passes (see
+ * nw_align_batch_banded).  The results are the same, every output included;
+ * the call is slower.  For comparison and testing. */
+#define NW_BAND_ONE_LAUNCH 0x8u
 
 /* Human-readable text for a status code (static storage). */
 const char *nw_strerror(int status);

@@ -33,6 +33,7 @@ MOVE_D, MOVE_U, MOVE_L = 1, 2, 3
 SCORE_ONLY = 0x1
 GRAPH = 0x2
 BAND_DOUBLING = 0x4
+BAND_ONE_LAUNCH = 0x8
 PAPER_SCORING = (1, -1, -1)
 
 NW_OK, NW_EINVAL, NW_ERANGE, NW_ENOSPC, NW_EDEVICE, NW_ENOTSUP = 0, -1, -2, -3, -4, -5
@@ -263,13 +264,17 @@ def align_batch_banded(pool: torch.Tensor, a_off: torch.Tensor, a_len: torch.Ten
                        scoring=PAPER_SCORING, w_init: torch.Tensor | None = None, w_default: int = 0,
                        fallback_frac: float = 0.5, score_only: bool = False,
                        path_off: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-                       stream=None, doubling: bool = False, cells_score_only: torch.Tensor | None = None):
+                       stream=None, doubling: bool = False, cells_score_only: torch.Tensor | None = None,
+                       one_launch: bool = False):
     """Certified-band batch.  Returns ``(scores, paths, path_off, path_len, w_used, status,
     cells)`` (paths/path_off/path_len are None with ``score_only``).  ``doubling``
     widens a failed band by doubling (NW_BAND_DOUBLING); ``cells_score_only``
-    (int64[npairs], optional) receives the cells swept score-only."""
+    (int64[npairs], optional) receives the cells swept score-only; ``one_launch``
+    runs the score-only first passes inside the launch with paths
+    (NW_BAND_ONE_LAUNCH: same results, slower)."""
     npairs = int(a_len.numel())
-    flags = (SCORE_ONLY if score_only else 0) | (BAND_DOUBLING if doubling else 0)
+    flags = ((SCORE_ONLY if score_only else 0) | (BAND_DOUBLING if doubling else 0)
+             | (BAND_ONE_LAUNCH if one_launch else 0))
     dev = _dev()
     ws = _workspace(banded_workspace_size(npairs, max_len, flags), workspace)
     scores = torch.empty(npairs, dtype=torch.int32, device=dev)
@@ -425,10 +430,11 @@ def learned_workspace_size(npairs: int, max_len: int, flags: int = 0) -> int:
 def align_batch_learned(pool, a_off, a_len, b_off, b_len, max_len: int, mlp: Mlp, margin: float = 0.0,
                         scoring=PAPER_SCORING, fallback_frac: float = 0.5, score_only: bool = False,
                         path_off=None, workspace=None, stream=None, doubling: bool = False,
-                        cells_score_only: torch.Tensor | None = None):
+                        cells_score_only: torch.Tensor | None = None, one_launch: bool = False):
     """Learned-band batch; same returns and options as ``align_batch_banded``."""
     npairs = int(a_len.numel())
-    flags = (SCORE_ONLY if score_only else 0) | (BAND_DOUBLING if doubling else 0)
+    flags = ((SCORE_ONLY if score_only else 0) | (BAND_DOUBLING if doubling else 0)
+             | (BAND_ONE_LAUNCH if one_launch else 0))
     dev = _dev()
     ws = _workspace(learned_workspace_size(npairs, max_len, flags), workspace)
     scores = torch.empty(npairs, dtype=torch.int32, device=dev)

@@ -1054,7 +1054,7 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, st, A.hist, A.cursor, A.n_narrow);
         hipLaunchKernelGGL(k_scatter<false>, dim3(pb), dim3(256), 0, st, A);
         if (job.banded) {
-            if (job.dirs && !job.band_doubling) launch_probe(A, L, di, job.njobs, st);
+            if (job.dirs && !job.band_doubling && !job.band_one_launch) launch_probe(A, L, di, job.njobs, st);
             if (job.dirs) launch_engine<true, false, true>(A, L.grid, st);
             else launch_engine<false, false, true>(A, L.grid, st);
         } else {

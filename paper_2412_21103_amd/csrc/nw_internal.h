@@ -86,6 +86,7 @@ struct BatchJob {
     // certified band
     bool banded;
     bool band_doubling;  // widen a failed band by doubling instead of to its certified width
+    bool band_one_launch;  // no separate launch of the score-only first passes
     const int32_t* w_init;
     int32_t w_default;
     int32_t frac_1024;

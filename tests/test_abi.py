@@ -108,3 +108,15 @@ def test_band_model_host_checks():
     assert L.nw_align_batch_learned(4, vp(1), vp(1), vp(1), vp(1), vp(1), 10, P, 0, ctypes.byref(st),
                                     f(0.1), f(0.5), vp(1), vp(1), vp(1), vp(1), vp(0), vp(0), vp(0),
                                     vp(0), vp(1), 1 << 30, vp(0)) == nwp.NW_EINVAL
+
+
+def test_flag_constants_match_header():
+    # the binding's flag values are the header's #defines
+    import re
+    text = open(nwp._HEADER).read()
+    defs = {k: int(v, 16) for k, v in re.findall(r"#define NW_([A-Z_]+) 0x([0-9a-fA-F]+)u", text)}
+    assert defs == {"SCORE_ONLY": nwp.SCORE_ONLY, "GRAPH": nwp.GRAPH, "BAND_DOUBLING": nwp.BAND_DOUBLING,
+                    "BAND_ONE_LAUNCH": nwp.BAND_ONE_LAUNCH}
+    # flags are distinct bits
+    vals = list(defs.values())
+    assert all(v & (v - 1) == 0 for v in vals) and len(set(vals)) == len(vals)

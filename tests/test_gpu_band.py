@@ -142,6 +142,46 @@ def test_band_directions_only_in_first_band(small_band_batch):
     assert (extra >= 2).sum() > 0
 
 
+@pytest.mark.parametrize("start", ["w0=0", "w0=40", "w_path", "w_cert"])
+def test_band_one_launch_same_outputs(small_band_batch, start):
+    # With paths, the score-only first passes run in a launch of their own and
+    # the launch with paths takes their results; every output (scores, paths,
+    # widths, statuses, cells, score-only cells) equals that of the schedule
+    # that runs all of a pair's passes in one launch.
+    pairs, ref = small_band_batch
+    if start.startswith("w0="):
+        w_init, w_default = None, int(start[3:])
+    else:
+        f = band.w_path if start == "w_path" else None
+        w_init = np.array([band.w_path(r[1], len(a), len(b)) if f else band.w_cert(r[0], len(a), len(b), P)
+                           for r, a, b in zip(ref, pairs.a, pairs.b)])
+        w_default = 0
+    out = {}
+    for one in (False, True):
+        say(f"band: {start}, one launch = {one}")
+        pool, ao, al, bo, bl = pack_pairs(pairs)
+        ml = int(max(al.max(), bl.max()))
+        so = torch.full((len(pairs),), -1, dtype=torch.int64, device="cuda")
+        wi = None if w_init is None else _dev(w_init, np.int32)
+        res = nwp.align_batch_banded(_dev(pool, np.uint8), _dev(ao, np.int64), _dev(al, np.int32),
+                                     _dev(bo, np.int64), _dev(bl, np.int32), ml, P, w_init=wi,
+                                     w_default=w_default, cells_score_only=so, one_launch=one)
+        torch.cuda.synchronize()
+        out[one] = [x.cpu().numpy() for x in res if x is not None] + [so.cpu().numpy()]
+    # the paths buffer beyond each path's length is never written: compare paths
+    for i, (x, y) in enumerate(zip(out[False], out[True])):
+        if i != 1:
+            assert np.array_equal(x, y), i
+    s, paths, poff, plen = out[False][:4]
+    paths1 = out[True][1]
+    for k in range(len(pairs)):
+        assert np.array_equal(paths[poff[k]:poff[k] + plen[k]], paths1[poff[k]:poff[k] + plen[k]]), k
+    check_equal(pairs, ref, s, [paths[poff[k]:poff[k] + plen[k]] for k in range(len(pairs))], start)
+    # the first passes that ran score-only are counted in the score-only cells
+    st = out[False][5]
+    assert (out[False][-1][(st & 0x40) == 0] > 0).all()
+
+
 def test_band_forced_fallback(small_band_batch):
     pairs, ref = small_band_batch
     say("band: fallback fraction tiny -> full grid")
