@@ -39,8 +39,14 @@
 
 namespace nw {
 
-constexpr int kCoopWaves = 4;
+constexpr int kCoopWaves = 4;  // waves per block of the traceback kernels
 constexpr int kCoopThreads = kWave * kCoopWaves;
+// Waves per block of the fill: consecutive strips, handing their boundary
+// column over through LDS rings inside the block and HBM slots between blocks.
+// Two (the 512 strips of a 65,536-column pair on all 256 CUs) measured
+// slower: half the hops then cross blocks (fill 4.57 against 4.23 ms).
+constexpr int kFillWaves = 4;
+constexpr int kFillThreads = kWave * kFillWaves;
 // Dynamic LDS request that leaves room for only one block per CU, so the
 // blocks spread over all CUs instead of doubling up.
 constexpr size_t kCoopDynLds = 96 * 1024;
@@ -68,12 +74,12 @@ struct CoopArgs {
 // rings' consumed-row counters.
 template <int C>
 struct CoopLds {
-    static constexpr int kTableWords = kCoopWaves * StripShape<C>::kLdsWords;
+    static constexpr int kTableWords = kFillWaves * StripShape<C>::kLdsWords;
     static constexpr int kTableWordsAligned = (kTableWords + 1) & ~1;
     static constexpr int kRingWords = 2 * kRing;
-    static constexpr int kSpareWord = kTableWordsAligned + kCoopWaves * kRingWords;
+    static constexpr int kSpareWord = kTableWordsAligned + kFillWaves * kRingWords;
     static constexpr int kCountWord = kSpareWord + 2;
-    static constexpr int kWords = kCountWord + kCoopWaves;
+    static constexpr int kWords = kCountWord + kFillWaves;
 };
 
 template <int C, bool DIRS, int IN, int OUT>
@@ -86,10 +92,10 @@ __device__ __forceinline__ int32_t coop_sweep(const CoopArgs& A, uint32_t epoch,
                                    col,
                                    col + A.bnd_stride - 1,
                                    rings + wave * kRing,
-                                   rings + ((wave + 1) % kCoopWaves) * kRing,
+                                   rings + ((wave + 1) % kFillWaves) * kRing,
                                    (lds_u64*)(dyn + CoopLds<C>::kSpareWord),
                                    consumed + wave,
-                                   consumed + (wave + 1) % kCoopWaves,
+                                   consumed + (wave + 1) % kFillWaves,
                                    A.m,
                                    A.vinit,
                                    epoch,
@@ -104,7 +110,7 @@ __device__ __forceinline__ int32_t coop_sweep(const CoopArgs& A, uint32_t epoch,
 }
 
 template <int C, bool DIRS>
-__global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
+__global__ __launch_bounds__(kFillThreads) void k_coop(CoopArgs A) {
     extern __shared__ uint32_t dyn[];
     __shared__ int ticket_s;
     const int wave = threadIdx.x >> 6;
@@ -124,11 +130,11 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
         const int k = uniform(ticket_s);
         // every wave is done with the previous group's rings: clear them and
         // their counters (row tags start at 1, so a zero slot is never ready)
-        for (int q = CoopLds<C>::kTableWordsAligned + threadIdx.x; q < CoopLds<C>::kWords; q += kCoopThreads)
+        for (int q = CoopLds<C>::kTableWordsAligned + threadIdx.x; q < CoopLds<C>::kWords; q += kFillThreads)
             ((__attribute__((address_space(3))) uint32_t*)dyn)[q] = 0;
         __syncthreads();
         if (k >= A.ngroups) break;
-        const int s = k * kCoopWaves + wave;
+        const int s = k * kFillWaves + wave;
         if (s < A.nstrips) {
             const int j0 = s * kCols;
             const int ksel = (A.n - 1 - j0) % C;
@@ -142,7 +148,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs A) {
             } else if (wave == 0) {
                 v = last ? coop_sweep<C, DIRS, kIoGlobal, kIoNone>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel)
                          : coop_sweep<C, DIRS, kIoGlobal, kIoLds>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel);
-            } else if (wave < kCoopWaves - 1) {
+            } else if (wave < kFillWaves - 1) {
                 v = last ? coop_sweep<C, DIRS, kIoLds, kIoNone>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel)
                          : coop_sweep<C, DIRS, kIoLds, kIoLds>(A, epoch, shift, wide, s, wave, lds, dyn, j0, ksel);
             } else {
@@ -569,7 +575,7 @@ static CoopLayout coop_layout(int64_t m, int64_t n, bool dirs) {
     CoopLayout L{};
     const int64_t cols = (int64_t)kWave * kCoopC;
     L.nstrips = (int)((n + cols - 1) / cols);
-    L.ngroups = (L.nstrips + kCoopWaves - 1) / kCoopWaves;
+    L.ngroups = (L.nstrips + kFillWaves - 1) / kFillWaves;
     L.G = groups_for_rows((int)m);
     L.bnd_stride = (int64_t)align_up((size_t)(m + 2), 32);  // rows 0..m and a spare slot
     L.seg_stride = (int64_t)align_up((size_t)(m + cols + 16), 64);
@@ -613,7 +619,7 @@ static hipError_t launch_coop_kernel(const CoopArgs& A, int grid, hipStream_t st
     }
     {
         ProfScope ps(DIRS ? "nw_fill_coop" : "nw_fill_coop_score", st);
-        hipLaunchKernelGGL((k_coop<kCoopC, DIRS>), dim3(grid), dim3(kCoopThreads), kCoopDynLds, st, A);
+        hipLaunchKernelGGL((k_coop<kCoopC, DIRS>), dim3(grid), dim3(kFillThreads), kCoopDynLds, st, A);
     }
     return hipGetLastError();
 }
