@@ -421,10 +421,10 @@ __device__ __forceinline__ int32_t fill_pair_mixed(const KArgs& A, const uint8_t
 #pragma unroll
         for (int k = 0; k < C; ++k) st[k] = (rs == 1) ? 0 : kNegW;
         bool st_v = false;  // domain of st
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
+        // the three ranges, each with its own sweep
+        auto range = [&](const int q) {
             const int rows = rb[q] - ra[q] + 1;
-            if (rows <= 0) continue;
+            if (rows <= 0) return;
             const bool vd = (q == 1);
             if (vd != st_v) {
 #pragma unroll
@@ -454,7 +454,10 @@ __device__ __forceinline__ int32_t fill_pair_mixed(const KArgs& A, const uint8_t
             last_v = vd;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        }
+        };
+        range(0);
+        range(1);
+        range(2);
         prev_lo = rs;
         prev_hi = re;
         swept += (int64_t)(re - rs + 1) * cols;
