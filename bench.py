@@ -135,7 +135,9 @@ def bench_band_batch(args):
     by wall time) -- the method without the network -- and (iii) the learned
     band, its margin chosen the same way.  The headline is arm (iii); every arm is compared
     with arm (i) on every score and path byte, and arm (iii) with the CPU
-    oracle on the cpu_baseline sample."""
+    oracle on the cpu_baseline sample.  A reference arm starts every test pair
+    at its own path's excursion (from arm (i)'s paths): what an exact width
+    predictor would give."""
     import ctypes
 
     import numpy as np
@@ -214,6 +216,16 @@ def bench_band_batch(args):
         if st != 0:
             raise nwp.NWError(st, "nw_align_batch_banded")
 
+    def exact(B, w_init, flags=0):
+        # every pair starts at its own optimal path's excursion: the start an
+        # exact width predictor would give (a reference for the learned one)
+        st = L.nw_align_batch_banded(B.n, *[ptr(v) for v in B.d], B.max_len, sc, flags, ptr(w_init), 0,
+                                     ctypes.c_float(frac), ptr(B.scores), ptr(B.paths), ptr(B.poff), ptr(B.plen),
+                                     ptr(B.w_used), ptr(B.status), ptr(B.swept), ptr(B.swept_so), ptr(ws), ws_bytes,
+                                     vp(stream.cuda_stream))
+        if st != 0:
+            raise nwp.NWError(st, "nw_align_batch_banded")
+
     def learned(B, net=None, mg=None, flags=0):
         net = mlp if net is None else net
         mg = margin if mg is None else mg
@@ -264,6 +276,10 @@ def bench_band_batch(args):
     print("bench: arm (i) full DP", file=sys.stderr, flush=True)
     wall_f, ms_f, prof_f = _events_timed(lambda: full(test), W, K, sync)
     ref = snapshot(test)
+    w_exact, _ = nwp.path_labels(test.paths, test.poff, test.plen, test.d[2], test.d[4])
+    print("bench: reference arm, every pair started at its own path's excursion", file=sys.stderr, flush=True)
+    wall_x, ms_x, prof_x = _events_timed(lambda: exact(test, w_exact), W, max(K // 2, 1), sync)
+    out_x = snapshot(test)
     print(f"bench: arm (ii) certified band from the constant w0 = {w0_best}", file=sys.stderr, flush=True)
     wall_c, ms_c, prof_c = _events_timed(lambda: const(test, w0_best), W, K, sync)
     out_c = snapshot(test)
@@ -276,6 +292,7 @@ def bench_band_batch(args):
     wall_l, ms_l, prof_l = _events_timed(lambda: learned(test), W, K, sync)
     out_l = snapshot(test)
     exact_c, exact_l = same(out_c, ref), same(out_l, ref)
+    exact_x = same(out_x, ref)
     exact_dbl = same(out_cd, ref) and same(out_ld, ref)
 
     def arm(name, wall, ms, prof, out, kernel):
@@ -307,6 +324,8 @@ def bench_band_batch(args):
     res_dbl_const["w0"] = w0_best_dbl
     res_dbl_const["w0_search_train_ms"] = {str(k): round(v, 2) for k, v in w0_ms_dbl.items()}
     res_dbl_learned = arm("dbl_learned", wall_ld, ms_ld, prof_ld, out_ld, "nw_batch_banded")
+    res_exact = arm("exact", wall_x, ms_x, prof_x, out_x, "nw_batch_banded")
+    res_exact["bit_exact_vs_full_dp"] = exact_x
 
     # roofline of the banded kernel in the learned arm: computed cells per launch
     # roofline of the banded kernel in the learned arm: the cells of the passes
@@ -358,6 +377,9 @@ def bench_band_batch(args):
               "learned_band": res_learned, "full_dp": res_full, "constant_band": res_const,
               "speedup_learned_vs_full_dp": round(wall_f / wall_l, 3),
               "speedup_learned_vs_constant_band": round(wall_c / wall_l, 3),
+              "exact_width_start": {**res_exact, "label": "w_init = each test pair's own w_path, from the "
+                                    "full-DP paths (the start an exact predictor would give; a reference)",
+                                    "learned_vs_exact_wall": round(wall_l / wall_x, 3)},
               "doubling": {"label": "w_cert", "margin": margin_cert, "learned_band": res_dbl_learned,
                            "constant_band": res_dbl_const,
                            "speedup_learned_vs_constant_band": round(wall_cd / wall_ld, 3),
