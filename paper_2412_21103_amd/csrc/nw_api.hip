@@ -603,9 +603,12 @@ int nw_autotune(int32_t npairs, const uint8_t* pool, const int64_t* a_off, const
 
 // ---------------------------------------------------------- certified band
 
+// the flags the banded and learned calls accept
+constexpr uint32_t kBandFlags = NW_SCORE_ONLY | NW_GRAPH | NW_BAND_DOUBLING | NW_BAND_ONE_LAUNCH;
+
 int nw_align_batch_banded_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags,
                                          size_t* bytes) {
-    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH | NW_BAND_DOUBLING | NW_BAND_ONE_LAUNCH)))
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~kBandFlags))
         return NW_EINVAL;
     DeviceInfo di;
     int st = device_info(&di);
@@ -656,7 +659,7 @@ static int check_banded(int32_t npairs, const uint8_t* pool, const int64_t* a_of
                         uint32_t flags, float fallback_frac, const int32_t* scores, const uint8_t* paths,
                         const int64_t* path_off, const int32_t* path_len, const void* ws,
                         bool ws_stream_ok) {
-    if (npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH | NW_BAND_DOUBLING | NW_BAND_ONE_LAUNCH))) return NW_EINVAL;
+    if (npairs < 0 || max_len < 0 || (flags & ~kBandFlags)) return NW_EINVAL;
     if ((flags & NW_GRAPH) && !ws_stream_ok) return NW_EINVAL;
     if (!(fallback_frac > 0.f) || fallback_frac > 64.f) return NW_EINVAL;
     const bool dirs = !(flags & NW_SCORE_ONLY);
@@ -819,7 +822,7 @@ static size_t learned_extra_bytes(int32_t npairs) {
 }
 
 int nw_align_batch_learned_workspace_size(int32_t npairs, int32_t max_len, uint32_t flags, size_t* bytes) {
-    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~(NW_SCORE_ONLY | NW_GRAPH | NW_BAND_DOUBLING | NW_BAND_ONE_LAUNCH)))
+    if (!bytes || npairs < 0 || max_len < 0 || (flags & ~kBandFlags))
         return NW_EINVAL;
     DeviceInfo di;
     int st = device_info(&di);

@@ -1,10 +1,13 @@
 // Persistent batch engine: many independent pairs (or the all-pairs matrix)
 // in one launch, one wave per pair.
 //
-// Jobs are ordered largest-first (by m*n, bucketed by log2) so the long pairs
-// start early and the tail is short.  Each wave owns a private slot of
-// workspace (boundary column, direction words, reversed path) and pulls jobs
-// from an atomic counter until none are left; every wave reaches the exit.
+// Jobs are ordered largest-first (by m*n, eight buckets per octave) so the
+// long pairs start early and the tail is short.  Each wave owns a private
+// slot of workspace (boundary column, direction words, reversed path) and
+// pulls jobs from an atomic counter until none are left; every wave reaches
+// the exit.  A banded call with paths first runs every pair's score-only
+// first pass in a launch of its own (k_probe), then orders the pairs again by
+// the cost of their remaining passes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -885,7 +888,8 @@ static Layout layout_for(int32_t njobs, int32_t max_len, bool dirs, const Device
     // covers the nseq <= njobs sequences of all-pairs
     const size_t mask_bytes = align_up((size_t)std::max(njobs, 1) * 2 * 32, 256);
     // the probe launch's records: a score (4 B) and a cell count (8 B) per job
-    const size_t probe_bytes = align_up((size_t)std::max(njobs, 1) * 4, 256) + align_up((size_t)std::max(njobs, 1) * 8, 256);
+    const size_t probe_bytes =
+        align_up((size_t)std::max(njobs, 1) * 4, 256) + align_up((size_t)std::max(njobs, 1) * 8, 256);
     const size_t fixed =
         align_up(kHeaderBytes + (size_t)std::max(njobs, 1) * 4, 256) + mask_bytes + probe_bytes + 3 * 256;
     const int64_t want = ((int64_t)njobs + kWavesPerBlock - 1) / kWavesPerBlock;
