@@ -955,10 +955,6 @@ static void launch_probe(KArgs& A, const Layout& L, const DeviceInfo& di, int32_
     const int64_t grid = std::min<int64_t>(std::min<int64_t>(want, (int64_t)di.cus * blocks_per_cu(false)), room);
     if (grid < 1) return;  // no room: k_batch sweeps the first passes itself
     A.probe_phase = 2;
-    // ordered by their remaining cost, the certified passes' first two rounds
-    // of jobs run at raised priority (learned band 35.5 -> 35.2 ms; none
-    // 35.6, three rounds 35.3, four 35.7)
-    A.prio_jobs = (int32_t)std::min<int64_t>(njobs, 2 * (int64_t)A.prio_jobs);
     KArgs P = A;
     P.probe_phase = 1;
     P.bnd = (int32_t*)A.dirs;
