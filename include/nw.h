@@ -37,8 +37,12 @@
  *  - Scores are int32.  Arguments are checked on the host before any GPU
  *    work is queued; a non-zero status means nothing was queued.
  *  - Overflow guard: (max(|match|,|mismatch|) + |gap|) * (m + n) must stay
- *    below 2^27, and the diagonal step constant 4*(s - 2*gap) + 2 must fit
- *    in a signed byte for s = match and s = mismatch, else NW_ERANGE.
+ *    below 2^27, |match|, |mismatch| and |gap| at most 2^20, and the cell's
+ *    diagonal term 4*(s - 2*gap) + 2 (s - 2*gap in score-only calls) below
+ *    2^22 in magnitude for s = match and s = mismatch, else NW_ERANGE.  When
+ *    a term does not fit in a signed byte (-127..127), the call sweeps every
+ *    pair by comparing bytes (about 7 instead of 5 operations per cell);
+ *    results are the same.
  *  - Calls on distinct streams with distinct workspaces may run concurrently.
  */
 #ifndef NW_H

@@ -83,14 +83,14 @@ int device_info(DeviceInfo* out, bool may_allocate) {
 }
 
 // Host checks shared by all entry points.
-static bool fits_byte(int32_t v) { return v >= -127 && v <= 127; }
-
 static int check_scoring(const nw_scoring& sc, bool dirs) {
     const int64_t big = 1 << 20;
     if (std::llabs(sc.match) > big || std::llabs(sc.mismatch) > big || std::llabs(sc.gap) > big)
         return NW_ERANGE;
+    // terms beyond a signed byte run the byte-comparing sweep (needs_wide),
+    // which holds them in 23 bits
     const Consts K = dirs ? dirs_consts(sc) : score_consts(sc);
-    if (!fits_byte(K.kdm) || !fits_byte(K.kdx)) return NW_ERANGE;
+    if (std::llabs(K.kdm) >= kWideTermLimit || std::llabs(K.kdx) >= kWideTermLimit) return NW_ERANGE;
     return NW_OK;
 }
 

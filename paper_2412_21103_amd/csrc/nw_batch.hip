@@ -81,6 +81,7 @@ struct KArgs {
     int32_t* probe_score;
     int64_t* probe_cells;
     int32_t probe_phase;
+    int32_t force_wide;  // every pair compares bytes (constants beyond a signed byte)
 };
 
 struct Pair {
@@ -238,8 +239,8 @@ __device__ __forceinline__ void mask_index(const Pair& p, int q, int64_t* qa, in
 template <bool ALLPAIRS>
 __device__ __forceinline__ int job_bucket(const KArgs& A, int q) {
     Pair p = get_pair<ALLPAIRS>(A, q);
-    bool wide = false;
-    if (p.m > 0 && p.n > 0) {
+    bool wide = A.force_wide != 0;
+    if (!wide && p.m > 0 && p.n > 0) {
         int64_t qa, qb;
         mask_index<ALLPAIRS>(p, q, &qa, &qb);
         wide = code_shift(A.masks + qa * 8, A.masks + qb * 8) < 0;
@@ -1027,6 +1028,7 @@ int launch_batch(const BatchJob& job, void* ws, size_t ws_bytes, hipStream_t st,
     A.status = job.status;
     A.cells = job.cells;
     A.cells_so = job.cells_so;
+    A.force_wide = needs_wide(K) ? 1 : 0;
     A.probe_phase = 0;
     A.probe_score = (int32_t*)(base + L.off_probe_score);
     A.probe_cells = (int64_t*)(base + L.off_probe_cells);

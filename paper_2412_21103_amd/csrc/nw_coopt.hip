@@ -92,6 +92,7 @@ struct CoArgs {
     int32_t prio_jobs; // the first prio_jobs single-wave jobs run at raised wave priority
     uint32_t* fault;   // host-visible device-fault word (may be null)
     uint32_t* masks;   // byte-presence masks: a of pair p at 16p, b at 16p+8
+    int32_t force_wide;  // every pair compares bytes (constants beyond a signed byte)
 };
 
 __device__ __forceinline__ int cost_bucket(int64_t cost) {
@@ -114,6 +115,7 @@ __global__ __launch_bounds__(256) void k_co_alpha(CoArgs A) {
 
 // The pair's code field (code_shift), or -1 to compare bytes.
 __device__ __forceinline__ int pair_shift(const CoArgs& A, int p) {
+    if (A.force_wide) return -1;
     return uniform(code_shift(A.masks + (int64_t)p * 16, A.masks + (int64_t)p * 16 + 8));
 }
 
@@ -679,6 +681,7 @@ int launch_cooptimal(int32_t npairs, const uint8_t* pool, const int64_t* a_off, 
     A.team_bucket = k > 0 ? kCoBuckets : NW_COOPT_TEAM_BUCKET;
     A.order = (int32_t*)(base + L.off_order);
     A.masks = (uint32_t*)(base + L.off_masks);
+    A.force_wide = needs_wide(K) ? 1 : 0;
     A.slots = base + L.off_slots;
     A.slot_bytes = L.slot_bytes;
     A.off_tie = L.off_tie;

@@ -18,6 +18,15 @@ struct Consts {
 Consts dirs_consts(const nw_scoring& sc);   // V domain: 4(s - 2 gap) + 2
 Consts score_consts(const nw_scoring& sc);  // W domain: s - 2 gap
 
+// The one-hot lookup holds a cell's diagonal terms as signed bytes (-128 is
+// the sentinel of rows outside the grid).  Constants outside -127..127 send
+// every pair of the call to the byte-comparing sweep, whose row word holds
+// the mismatch term in 23 bits and which takes the match term whole.
+inline bool needs_wide(const Consts& K) {
+    return K.kdm < -127 || K.kdm > 127 || K.kdx < -127 || K.kdx > 127;
+}
+constexpr int32_t kWideTermLimit = 1 << 22;  // |term| below this for the byte-comparing sweep
+
 // Device facts needed to size persistent grids, and the per-call settings
 // every launch carries: the device-fault word and the polls a bounded wait
 // makes before it gives up.

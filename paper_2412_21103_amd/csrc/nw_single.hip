@@ -67,6 +67,7 @@ struct CoopArgs {
     int32_t* score;
     uint32_t* fault;        // host-visible device-fault word (may be null)
     const uint32_t* masks;  // byte-presence masks of a and b (eight words each), written by k_coop_alpha
+    int32_t force_wide;     // compare bytes whatever the masks say (constants beyond a signed byte)
 };
 
 // Dynamic LDS of a block: the waves' row tables, then one boundary ring per
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(kFillThreads) void k_coop(CoopArgs A) {
                                                                           __HIP_MEMORY_SCOPE_AGENT));
     // the pair's code field, or compared bytes
     const int shift_or = uniform(code_shift(A.masks, A.masks + 8));
-    const bool wide = shift_or < 0;
+    const bool wide = A.force_wide != 0 || shift_or < 0;
     const uint32_t shift = (uint32_t)max(shift_or, 0);
     for (;;) {
         if (threadIdx.x == 0) ticket_s = atomicAdd(A.ticket, 1);
@@ -654,6 +655,7 @@ int launch_coop(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n, const 
     A.score = score;
     A.fault = di.fault;
     A.masks = (const uint32_t*)(hdr + kHdrMasks);
+    A.force_wide = needs_wide(K) ? 1 : 0;
     hipLaunchKernelGGL(k_prep, dim3(1), dim3(128), 0, st, hdr, next_epoch());
     {
         const int64_t chunks = (m + kAlphaChunk - 1) / kAlphaChunk + (n + kAlphaChunk - 1) / kAlphaChunk;

@@ -48,8 +48,9 @@ def test_host_argument_checks():
     assert _align(ws=0) == nwp.NW_EINVAL
     assert _align(cap=7) == nwp.NW_ENOSPC
     assert _align(flags=0x80) == nwp.NW_EINVAL
-    # diagonal constant 4*(s - 2 gap) + 2 outside a signed byte
-    assert _align(sc=nwp.Scoring(40, -1, -1)) == nwp.NW_ERANGE
+    # diagonal term 4*(s - 2 gap) + 2 at or beyond 2^22 (terms beyond a
+    # signed byte alone are legal: they take the byte-comparing sweep)
+    assert _align(sc=nwp.Scoring(1 << 20, -1, -1)) == nwp.NW_ERANGE
     # overflow guard on lengths
     assert _align(m=1 << 27, n=1 << 27, cap=1 << 28) == nwp.NW_ERANGE
     vp = ctypes.c_void_p
