@@ -101,3 +101,30 @@ def test_allpairs_and_cooptimal_wide_scoring(sc):
     assert np.array_equal(scores, s_ref)
     assert np.array_equal(counts.view(np.uint64), c_ref)
     assert np.array_equal(sat, f_ref)
+
+
+@pytest.mark.parametrize("sc", SCORINGS)
+def test_center_star_wide_scoring(sc):
+    from oracle import msa as omsa
+    rng = np.random.default_rng(7)
+    root = rng.integers(0, 4, 500).astype(np.uint8)
+    seqs = []
+    for _ in range(10):
+        s = root.copy()
+        k = rng.random(len(s)) < 0.1
+        s[k] = rng.integers(0, 4, int(k.sum())).astype(np.uint8)
+        keep = rng.random(len(s)) >= 0.03
+        seqs.append(s[keep][: int(rng.integers(200, 500))].copy())
+    pool, off, lens = pack_seqs(seqs)
+    ml = int(lens.max())
+    say(f"wide scoring {sc}: centre star")
+    dp, do, dl = _dev(pool, np.uint8), _dev(off, np.int64), _dev(lens, np.int32)
+    S = nwp.allpairs(dp, do, dl, ml, sc)
+    c, M, w = nwp.center_star(dp, do, dl, ml, S, sc, gap_byte=255)
+    torch.cuda.synchronize()
+    c_ref, M_ref = omsa.center_star(seqs, sc, gap_byte=255, scores=S.cpu().numpy())
+    assert np.array_equal(S.cpu().numpy(), oracle.allpairs(pool, off, lens, sc))
+    assert int(c.item()) == c_ref
+    w = int(w.item())
+    assert w == M_ref.shape[1]
+    assert np.array_equal(M.cpu().numpy()[:, :w], M_ref)
